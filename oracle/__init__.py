@@ -1,0 +1,110 @@
+"""FP64 CPU oracle for the all-families regression scores -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this package.  The GPU library never imports, links or calls it.
+
+`oracle.c` solves each family on its own by Householder QR (the brute-force
+route of Sec. 1.1 of the paper); `walk.py` holds the integer reference for the
+swap sequences of Sec. 3 and Sec. 6.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+OUT_BIC = 0
+OUT_RSS = 1
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(path)
+        i64, dbl, vp = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+        lib.or_num_families.argtypes = [ctypes.c_int]
+        lib.or_num_families.restype = i64
+        lib.or_family_index.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64]
+        lib.or_family_index.restype = i64
+        lib.or_family_decode.argtypes = [ctypes.c_int, i64, ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_uint64)]
+        lib.or_family_decode.restype = ctypes.c_int
+        lib.or_bic.argtypes = [dbl, i64, ctypes.c_int]
+        lib.or_bic.restype = dbl
+        lib.or_rss.argtypes = [vp, i64, ctypes.c_int, i64, ctypes.c_int, ctypes.c_uint64]
+        lib.or_rss.restype = dbl
+        lib.or_score_all.argtypes = [vp, i64, ctypes.c_int, i64, vp, ctypes.c_int, ctypes.c_int]
+        lib.or_score_all.restype = ctypes.c_int
+        lib.or_score_indices.argtypes = [vp, i64, ctypes.c_int, i64, vp, i64, vp, ctypes.c_int,
+                                         ctypes.c_int]
+        lib.or_score_indices.restype = ctypes.c_int
+        _LIB = lib
+    return _LIB
+
+
+def _as_X(X):
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    if X.ndim != 2:
+        raise ValueError("X must be 2-D (n, m)")
+    return X
+
+
+def default_threads() -> int:
+    return max(1, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count() or 1)
+
+
+def num_families(m: int) -> int:
+    return int(_lib().or_num_families(m))
+
+
+def family_index(m: int, child: int, mask: int) -> int:
+    return int(_lib().or_family_index(m, child, mask))
+
+
+def family_decode(m: int, idx: int):
+    c = ctypes.c_int()
+    mk = ctypes.c_uint64()
+    if _lib().or_family_decode(m, idx, ctypes.byref(c), ctypes.byref(mk)) != 0:
+        raise ValueError("index out of range")
+    return c.value, mk.value
+
+
+def bic(rss: float, n: int, nparents: int) -> float:
+    return float(_lib().or_bic(rss, n, nparents))
+
+
+def rss(X, child: int, mask: int) -> float:
+    X = _as_X(X)
+    n, m = X.shape
+    return float(_lib().or_rss(X.ctypes.data, n, m, m, child, mask))
+
+
+def score_all(X, what: int = OUT_BIC, threads: int | None = None) -> np.ndarray:
+    X = _as_X(X)
+    n, m = X.shape
+    out = np.empty(num_families(m), dtype=np.float64)
+    st = _lib().or_score_all(X.ctypes.data, n, m, m, out.ctypes.data, what,
+                             threads or default_threads())
+    if st != 0:
+        raise RuntimeError(f"oracle score_all failed ({st})")
+    return out
+
+
+def score_indices(X, idx, what: int = OUT_BIC, threads: int | None = None) -> np.ndarray:
+    X = _as_X(X)
+    n, m = X.shape
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    out = np.empty(idx.shape[0], dtype=np.float64)
+    st = _lib().or_score_indices(X.ctypes.data, n, m, m, idx.ctypes.data, idx.shape[0],
+                                 out.ctypes.data, what, threads or default_threads())
+    if st != 0:
+        raise RuntimeError(f"oracle score_indices failed ({st})")
+    return out
