@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the whole hot path on one MI355X.
+
+One step = one gs_score_all call on data already resident in HBM: R0 by TSQR (FP64),
+the segment anchors (FP64), the FP32 Givens walk and the write of the complete score
+table (m * 2^(m-1) BIC values).  Workload: m = 26 variables, n = 5000 samples from a
+seeded linear-Gaussian DAG (edge probability 0.15, weights +-U[0.3, 1.0]);
+872,415,232 families, a 3.49 GB FP32 table.
+
+Prints one JSON line.  Besides the contract fields it carries
+  roofline      the walk kernel against the HBM write roofline (4 algorithmic
+                bytes per family), timed with HIP events on the launch stream;
+  valu          the walk's algorithmic FP32 flops against the FP32 vector peak;
+  fp64_walk     the same step with the walk in FP64 (families/s);
+  fp32_vs_fp64  max relative RSS difference of the two walks over the whole table;
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+WORKLOADS = {"c3_m26_n5000": "c3_m26_n5000", "c2_m20_n1000": "c2_m20_n1000"}
+
+
+def runtime_T(m: int) -> int:
+    """Flops of the paper's serial walk (Sec. 5 closed form, middle term 6 * 2^m)."""
+    return 3 * m * (1 << m) + 6 * (1 << m) - 3 * m * m - 9 * m - 6
+
+
+def walk_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("walk.hip", "walk_program.hpp"):
+        with open(os.path.join(ROOT, "paper_1901_07643_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per walk launch from the committed PMC summary, if it was taken on
+    the current walk kernel source."""
+    path = os.path.join(ROOT, "profiles", f"walk_f32_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("walk_source_hash") != walk_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(X, m, sample: int, seed: int = 1):
+    import numpy as np
+
+    import oracle
+    threads = oracle.default_threads()
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(m * (1 << (m - 1)), size=sample, replace=False).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.score_indices(X, idx, oracle.OUT_BIC, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "families/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample} uniformly drawn families of the same table (BIC, FP64 "
+                      f"Householder per family), {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c3_m26_n5000", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-sample", type=int, default=131072)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-walk comparison")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1901_07643_amd as gs
+    from datagen import CONFIGS, config_data
+
+    cfg = CONFIGS[args.workload]
+    m, n = cfg.m, cfg.n
+    X_host = config_data(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X = torch.as_tensor(X_host, device=dev)
+    plan = gs.Plan(m)
+    info = plan.info
+    nfam = gs.num_families(m)
+    out = torch.empty(nfam, dtype=torch.float32, device=dev)
+    print(f"# workload {args.workload}: m={m} n={n} families={nfam} plan={info}", file=sys.stderr,
+          flush=True)
+
+    if args.calib_copy_mb:
+        nb = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(nb, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for _ in range(args.warmup):
+        gs.score_all(X, plan=plan, what="bic", precision="fp32", out=out, check_status=False)
+    torch.cuda.synchronize()
+    st = plan.status()
+    if st != gs.GS_OK:
+        raise SystemExit(f"device status {st}: {gs.last_error()}")
+
+    plan.set_timing(True)
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        gs.score_all(X, plan=plan, what="bic", precision="fp32", out=out, check_status=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    stage_ms, cnt = plan.timing()
+    plan.set_timing(False)
+    print(f"# timed {args.steps} steps: {ms_step:.4f} ms/step (wall {wall:.3f} s); stages "
+          f"qr {stage_ms[0]:.4f} anchors {stage_ms[1]:.4f} walk {stage_ms[2]:.4f} ms",
+          file=sys.stderr, flush=True)
+
+    value = nfam / (ms_step * 1e-3)
+    walk_s = stage_ms[2] * 1e-3
+    alg_bytes = 4.0 * nfam                       # one FP32 table write per family
+    achieved_gbs = alg_bytes / walk_s / 1e9
+    traffic = load_traffic(args.workload)
+    alg_flops = runtime_T(m) + 4.0 * nfam        # Givens steps + RSS and BIC per family
+    valu_tflops = alg_flops / walk_s / 1e12
+
+    res = {
+        "metric": "families scored/s (BIC) at m=26,n=5000" if args.workload == "c3_m26_n5000"
+        else f"families scored/s (BIC) at m={m},n={n}",
+        "value": value,
+        "unit": "families/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "families": nfam,
+                   "edge_prob": cfg.p_edge, "weights": [cfg.lo, cfg.hi], "seed": cfg.seed,
+                   "walk": "fp32", "anchors": "fp64", "output": "bic",
+                   "plan": {"k": info["k"], "ks": info["ks"], "segments": info["num_segments"]}},
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": "walk_kernel<float,5,true>",
+                     "kernel_ms": stage_ms[2]},
+        "valu": {"achieved": valu_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": valu_tflops / FP32_VECTOR_PEAK_TFLOPS},
+        "stages_ms": {"r0_qr": stage_ms[0], "anchors": stage_ms[1], "walk": stage_ms[2],
+                      "call": stage_ms[3]},
+    }
+
+    if not args.no_fp64:
+        out64 = torch.empty(nfam, dtype=torch.float64, device=dev)
+        gs.score_all(X, plan=plan, what="bic", precision="fp64", out=out64, check_status=False)
+        torch.cuda.synchronize()
+        k64 = max(2, args.steps // 4)
+        e0.record(stream)
+        for _ in range(k64):
+            gs.score_all(X, plan=plan, what="bic", precision="fp64", out=out64, check_status=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms64 = e0.elapsed_time(e1) / k64
+        res["fp64_walk"] = {"value": nfam / (ms64 * 1e-3), "unit": "families/s",
+                            "ms_per_step": ms64, "steps": k64}
+        gs.score_all(X, plan=plan, what="rss", precision="fp64", out=out64, check_status=False)
+        gs.score_all(X, plan=plan, what="rss", precision="fp32", out=out, check_status=False)
+        worst = 0.0
+        for lo in range(0, nfam, 1 << 27):
+            hi = min(nfam, lo + (1 << 27))
+            rel = ((out[lo:hi].double() - out64[lo:hi]).abs() / out64[lo:hi]).max().item()
+            worst = max(worst, rel)
+        res["fp32_vs_fp64"] = {"max_rel_rss_err": worst, "over": "whole table"}
+        del out64
+        torch.cuda.synchronize()
+        print(f"# fp64 walk {ms64:.4f} ms/step; max rel RSS fp32 vs fp64 {worst:.3e}",
+              file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        print(f"# cpu baseline: oracle on {args.cpu_sample} families ...", file=sys.stderr,
+              flush=True)
+        res["cpu_baseline"] = cpu_baseline(X_host, m, args.cpu_sample)
+    else:
+        res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

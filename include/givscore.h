@@ -1,0 +1,152 @@
+/*
+ * givscore -- least-squares scores of every family (child, parent set) of m
+ * variables by a walk over QR decompositions with Givens retriangularisations.
+ *
+ * The method (Alipourfard & Gao, "Solving All Regression Models For Learning
+ * Gaussian Networks Using Givens Rotations"):
+ *   - one QR decomposition of the n x m data matrix X (Sec. 2: the algorithm
+ *     starts from the QRD of the data);
+ *   - a sequence of adjacent column transpositions, each followed by one Givens
+ *     rotation that restores the triangular R (Sec. 1.3, the GRC operator);
+ *   - every R visited solves the regressions "prefix -> later variable" of its
+ *     column ordering (Sec. 2); the sequence is the shortest one that visits every
+ *     parent set (Sec. 3 recursion, Sec. 4 optimality), split into independent
+ *     pieces that start from their own QRD (Sec. 6).
+ *
+ * Family set and table layout (the paper leaves both implicit):
+ *   families: child c in 0..m-1, parent set S any subset of the other m-1
+ *             variables, the empty set included: m * 2^(m-1) families (Sec. 1).
+ *   index(c, S) = c * 2^(m-1) + compress(S, c), where compress removes bit c of
+ *             the bitmask S (bit v = variable / column v) and shifts the higher
+ *             bits down by one.  gs_family_index() computes it.
+ *   RSS(c, S) = min_beta || x_c - X_S beta ||^2  (no intercept; X used as given).
+ *   BIC(c, S) = n ln(RSS / n) + (|S| + 2) ln n   (lower is better).
+ *
+ * Conventions for every entry point:
+ *   - Return value: GS_OK (0) or a negative gs_status.  Argument errors are found
+ *     before any device work and leave every output untouched.  gs_last_error()
+ *     gives a message for the calling thread's last failure.
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary host memory.  The caller owns every pointer it passes.
+ *     The library owns the plan and its device workspace; gs_plan_destroy frees them.
+ *   - stream: a hipStream_t passed as void* (NULL = the default stream).  Device
+ *     work is enqueued asynchronously on it; outputs are valid once the stream has
+ *     reached that point.  Data-dependent conditions found on the device (rank
+ *     deficiency, non-finite input) are reported by gs_sync_status().
+ *   - A plan may be used by one stream at a time (its workspace is shared).
+ */
+#ifndef GIVSCORE_H
+#define GIVSCORE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gs_plan_s gs_plan_t;
+
+typedef enum {
+    GS_OK = 0,
+    GS_EINVAL = -1,      /* bad argument: null pointer, size or range            */
+    GS_ERANK = -2,       /* R0 has a (near) zero diagonal: X is rank deficient    */
+    GS_ENOMEM = -3,      /* device workspace could not be allocated               */
+    GS_EHIP = -4,        /* a HIP runtime call failed                             */
+    GS_ENOTFINITE = -5   /* X holds NaN or Inf                                    */
+} gs_status;
+
+typedef enum { GS_OUT_BIC = 0, GS_OUT_RSS = 1 } gs_output;
+
+/* Largest number of variables supported (the FP32 table then takes 64 GB). */
+#define GS_MAX_M 30
+
+typedef struct {
+    int m;                      /* variables                                          */
+    int k;                      /* variables walked inside one segment (Sec. 6: m - k
+                                   variables are fixed in front or at the back)       */
+    int ks;                     /* inner block: the lowest ks labels, walked by the
+                                   paper's sequence for ks variables                  */
+    int q;                      /* k - ks middle variables, walked by the same
+                                   sequence one level up                              */
+    int64_t num_segments;       /* 2^(m-k) independent segments                       */
+    int64_t sub_per_segment;    /* 2^q inner walks per segment                        */
+    int64_t swaps_per_segment;  /* Givens steps per segment: 2^k - k - 1              */
+    int64_t num_families;       /* m * 2^(m-1)                                        */
+} gs_plan_info_t;
+
+/* Number of families m * 2^(m-1); -1 if m is outside 1..GS_MAX_M. */
+int64_t gs_num_families(int m);
+
+/* Table index of (child, parent_mask); -1 if child is out of range, bit `child`
+ * is set in parent_mask, or parent_mask has bits at or above m. */
+int64_t gs_family_index(int m, int child, uint64_t parent_mask);
+
+/* The paper's swap sequence Upsilon(m) (Sec. 3 recursion with the "+1" shift,
+ * Sec. 5 recurrence): 1-based indices i, each exchanging positions i and i+1.
+ * Writes min(cap, 2^m - m - 1) entries to out (host) and returns the full length,
+ * or GS_EINVAL for m outside 1..24. */
+int64_t gs_upsilon(int m, int32_t *out, int64_t cap);
+
+/* Create a plan for m variables (1..GS_MAX_M) with the default segment sizes.
+ * Host-only integer work; no device memory is touched until the first score call.
+ * *out receives a library-owned handle. */
+int gs_plan(int m, gs_plan_t **out);
+
+/* Same with explicit sizes: 1 <= ks <= 6, ks <= m, ks <= k <= m, k - ks <= 16.
+ * ks = 0 or k = 0 selects the default for that size. */
+int gs_plan_tuned(int m, int k, int ks, gs_plan_t **out);
+
+/* Free a plan and its device workspace (NULL is ignored).  The device work it
+ * enqueued must have finished. */
+void gs_plan_destroy(gs_plan_t *plan);
+
+/* Sizes chosen by the plan (host struct). */
+int gs_plan_get_info(const gs_plan_t *plan, gs_plan_info_t *info);
+
+/* Host simulation of the plan's walk: counts[index] += 1 for every family the
+ * kernels will write (counts: host, len >= m * 2^(m-1)).  A correct plan leaves
+ * every entry incremented exactly once.  For testing the planner; m <= 22. */
+int gs_plan_count_emissions(const gs_plan_t *plan, int32_t *counts, int64_t len);
+
+/* R0 = the triangular factor of the QR decomposition of X (Sec. 2, the initial
+ * QRD), FP64, with a non-negative diagonal.
+ *   X: device, n x m, row-major, row stride ldx >= m (elements), n > m.
+ *   R0: device, m x m row-major; the strict lower triangle is set to zero. */
+int gs_qr_r0(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
+             double *R0, void *stream);
+
+/* Scores of all m * 2^(m-1) families with the walk in FP32 (segment starts in FP64).
+ *   X: device, n x m row-major FP64, row stride ldx >= m, n > m; m must equal the
+ *      plan's m.
+ *   scores: device, m * 2^(m-1) floats, 16-byte aligned, written in table order
+ *      (every entry exactly once).
+ *   what: GS_OUT_BIC or GS_OUT_RSS. */
+int gs_score_all(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
+                 float *scores, int what, void *stream);
+
+/* Same, with the whole walk in FP64 and an FP64 table (16-byte aligned). */
+int gs_score_all_f64(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
+                     double *scores, int what, void *stream);
+
+/* Wait for the plan's last enqueued work and return GS_OK, GS_ERANK or
+ * GS_ENOTFINITE from the device status word of that call (GS_EHIP on a runtime
+ * failure). */
+int gs_sync_status(gs_plan_t *plan);
+
+/* Per-stage timing with HIP events recorded on the call's stream.  enable != 0
+ * starts recording (and clears old records). */
+int gs_set_timing(gs_plan_t *plan, int enable);
+
+/* Waits for the recorded events and returns, for the calls recorded since the last
+ * gs_set_timing, the mean milliseconds of: ms[0] R0 QR, ms[1] segment anchors,
+ * ms[2] walk kernel, ms[3] whole call (host arrays of 4).  *count = calls averaged. */
+int gs_get_timing(gs_plan_t *plan, double *ms, int64_t *count);
+
+/* Message for the calling thread's last error ("" if none). */
+const char *gs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GIVSCORE_H */

@@ -1,0 +1,162 @@
+"""givscore: scores of every (child, parent set) family of m variables by the
+Givens-rotation walk over QR decompositions, as hand-written HIP kernels for
+MI355X (gfx950).
+
+This module is a thin binding over the C ABI in include/givscore.h: it marshals
+torch device tensors into pointers and the current HIP stream; every step of the
+computation runs in libgivscore.so.  PyTorch only provides device memory and
+streams.
+
+    X = torch.as_tensor(data, dtype=torch.float64, device="cuda")   # (n, m)
+    table = score_all(X)               # (m * 2^(m-1),) float32 BIC, FP32 walk
+    rss = score_all(X, what="rss", precision="fp64")
+
+Table order: index(c, S) = c * 2^(m-1) + compress(S, c), see family_index().
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._abi import (GS_EINVAL, GS_ENOTFINITE, GS_ERANK, GS_MAX_M, GS_OK, GS_OUT_BIC, GS_OUT_RSS,
+                   GivScoreError, PlanInfo, check, last_error, lib)
+
+__all__ = [
+    "Plan", "score_all", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
+    "GS_OK", "GS_EINVAL", "GS_ERANK", "GS_ENOTFINITE", "GS_MAX_M", "lib", "last_error",
+]
+
+
+def num_families(m: int) -> int:
+    r = lib().gs_num_families(m)
+    if r < 0:
+        raise GivScoreError(GS_EINVAL, f"m={m} out of range")
+    return int(r)
+
+
+def family_index(m: int, child: int, parent_mask: int) -> int:
+    r = lib().gs_family_index(m, child, parent_mask)
+    if r < 0:
+        raise GivScoreError(GS_EINVAL, "bad family")
+    return int(r)
+
+
+def upsilon(m: int) -> list[int]:
+    """The paper's swap sequence (1-based), from the library's planner."""
+    n = check(lib().gs_upsilon(m, None, 0))
+    buf = (ctypes.c_int32 * max(1, n))()
+    check(lib().gs_upsilon(m, buf, n))
+    return list(buf[:n])
+
+
+class Plan:
+    """Library-owned plan for m variables (segment split and walk program)."""
+
+    def __init__(self, m: int, k: int = 0, ks: int = 0):
+        h = ctypes.c_void_p()
+        check(lib().gs_plan_tuned(m, k, ks, ctypes.byref(h)))
+        self._h = h
+        self.m = m
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("plan destroyed")
+        return self._h
+
+    @property
+    def info(self) -> dict:
+        inf = PlanInfo()
+        check(lib().gs_plan_get_info(self.handle, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+
+    def count_emissions(self) -> np.ndarray:
+        """Host simulation of the walk: how often each table entry would be written."""
+        counts = np.zeros(num_families(self.m), dtype=np.int32)
+        check(lib().gs_plan_count_emissions(
+            self.handle, counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), counts.size))
+        return counts
+
+    def status(self) -> int:
+        """Wait for the last call and return its device status code (0, GS_ERANK,
+        GS_ENOTFINITE)."""
+        return int(lib().gs_sync_status(self.handle))
+
+    def set_timing(self, enable: bool = True):
+        check(lib().gs_set_timing(self.handle, 1 if enable else 0))
+
+    def timing(self):
+        """Mean ms of (R0 QR, anchors, walk, whole call) over the recorded calls."""
+        ms = (ctypes.c_double * 4)()
+        cnt = ctypes.c_int64()
+        check(lib().gs_get_timing(self.handle, ms, ctypes.byref(cnt)))
+        return list(ms), int(cnt.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().gs_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_X(X, m_expected=None):
+    import torch
+    if not isinstance(X, torch.Tensor) or X.device.type != "cuda":
+        raise TypeError("X must be a torch tensor on a HIP device")
+    if X.dtype != torch.float64 or X.dim() != 2:
+        raise TypeError("X must be a 2-D float64 tensor (n, m)")
+    if X.stride(1) != 1:
+        raise ValueError("X must have unit column stride (row-major)")
+    n, m = X.shape
+    if m_expected is not None and m != m_expected:
+        raise ValueError("X has a different m than the plan")
+    return n, m, X.stride(0)
+
+
+def _stream(dev):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def qr_r0(X, plan: Plan | None = None):
+    """R factor (m x m, FP64, non-negative diagonal) of the QR decomposition of X."""
+    import torch
+    n, m, ldx = _check_X(X, plan.m if plan else None)
+    plan = plan or Plan(m)
+    R = torch.empty((m, m), dtype=torch.float64, device=X.device)
+    with torch.cuda.device(X.device):
+        check(lib().gs_qr_r0(plan.handle, ctypes.c_void_p(X.data_ptr()), n, m, ldx,
+                             ctypes.c_void_p(R.data_ptr()), _stream(X.device)))
+    return R
+
+
+def score_all(X, plan: Plan | None = None, what: str = "bic", precision: str = "fp32", out=None,
+              check_status: bool = True):
+    """All m * 2^(m-1) family scores of X (device tensor (n, m) float64).
+
+    what: "bic" or "rss".  precision: "fp32" (FP32 walk, FP32 table) or "fp64"
+    (FP64 walk, FP64 table).  With check_status the call waits for the device and
+    raises GivScoreError on rank-deficient or non-finite X."""
+    import torch
+    n, m, ldx = _check_X(X, plan.m if plan else None)
+    plan = plan or Plan(m)
+    w = {"bic": GS_OUT_BIC, "rss": GS_OUT_RSS}[what]
+    dtype = {"fp32": torch.float32, "fp64": torch.float64}[precision]
+    N = num_families(m)
+    if out is None:
+        out = torch.empty(N, dtype=dtype, device=X.device)
+    elif out.dtype != dtype or out.numel() != N or not out.is_contiguous() or out.device != X.device:
+        raise ValueError("out must be a contiguous tensor of m*2^(m-1) elements of the right dtype")
+    fn = lib().gs_score_all if precision == "fp32" else lib().gs_score_all_f64
+    with torch.cuda.device(X.device):
+        check(fn(plan.handle, ctypes.c_void_p(X.data_ptr()), n, m, ldx,
+                 ctypes.c_void_p(out.data_ptr()), w, _stream(X.device)))
+        if check_status:
+            check(plan.status())
+    return out

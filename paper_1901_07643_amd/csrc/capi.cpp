@@ -1,0 +1,236 @@
+// C-ABI entry points of libgivscore that touch the device: argument checks,
+// workspace management, the launch sequence R0 -> anchors -> walk, the status
+// word and the per-stage timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "gs_internal.hpp"
+
+using namespace gs;
+
+namespace {
+
+__global__ void zero_status_kernel(int *st) {
+    if (threadIdx.x == 0) st[0] = 0;
+}
+
+void free_device(gs_plan_s *p) {
+    if (p->done) (void)hipEventDestroy(p->done);
+    for (auto &ev : p->events)
+        for (auto e : ev) (void)hipEventDestroy(e);
+    p->events.clear();
+    (void)hipFree(p->d_prog);
+    (void)hipFree(p->d_r0);
+    (void)hipFree(p->d_qr_a);
+    (void)hipFree(p->d_qr_b);
+    (void)hipFree(p->d_anchor);
+    (void)hipFree(p->d_tail);
+    (void)hipFree(p->d_status);
+    p->d_prog = nullptr;
+    p->d_r0 = p->d_qr_a = p->d_qr_b = p->d_anchor = p->d_tail = nullptr;
+    p->d_status = nullptr;
+    p->done = nullptr;
+    p->qr_cap = 0;
+    p->device = -1;
+}
+
+int ensure_workspace(gs_plan_s *p, int64_t n) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (p->device >= 0 && p->device != dev)
+        return fail(GS_EINVAL, "plan was first used on another device");
+    if (p->device < 0) {
+        p->device = dev;
+        const size_t prog_b = p->prog.size() * sizeof(uint32_t);
+        const size_t r0_b = size_t(p->m) * p->m * sizeof(double);
+        const size_t an_b = size_t(p->nseg) * p->k * 32 * sizeof(double);
+        const size_t tl_b = size_t(p->nseg) * 32 * sizeof(double);
+        if ((e = hipMalloc(&p->d_prog, prog_b)) != hipSuccess ||
+            (e = hipMalloc(&p->d_r0, r0_b)) != hipSuccess ||
+            (e = hipMalloc(&p->d_anchor, an_b)) != hipSuccess ||
+            (e = hipMalloc(&p->d_tail, tl_b)) != hipSuccess ||
+            (e = hipMalloc(&p->d_status, sizeof(int) * 4)) != hipSuccess) {
+            free_device(p);
+            return fail(GS_ENOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));
+        }
+        if ((e = hipMemcpy(p->d_prog, p->prog.data(), prog_b, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemset(p->d_status, 0, sizeof(int) * 4)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming)) != hipSuccess) {
+            free_device(p);
+            return hip_fail(e, "workspace initialisation");
+        }
+    }
+    const int64_t need = qr_workspace_elems(n, p->m);
+    if (need > p->qr_cap) {
+        (void)hipFree(p->d_qr_a);
+        (void)hipFree(p->d_qr_b);
+        p->d_qr_a = p->d_qr_b = nullptr;
+        p->qr_cap = 0;
+        if ((e = hipMalloc(&p->d_qr_a, size_t(need) * sizeof(double))) != hipSuccess ||
+            (e = hipMalloc(&p->d_qr_b, size_t(need) * sizeof(double))) != hipSuccess) {
+            (void)hipFree(p->d_qr_a);
+            p->d_qr_a = nullptr;
+            return fail(GS_ENOMEM, std::string("QR workspace allocation failed: ") + hipGetErrorString(e));
+        }
+        p->qr_cap = need;
+    }
+    return GS_OK;
+}
+
+int check_common(gs_plan_s *p, const void *X, int64_t n, int m, int64_t ldx, const void *out,
+                 const char *who) {
+    const std::string w(who);
+    if (!p) return fail(GS_EINVAL, w + ": plan is NULL");
+    if (!X || !out) return fail(GS_EINVAL, w + ": NULL data pointer");
+    if (m != p->m) return fail(GS_EINVAL, w + ": m differs from the plan's m");
+    if (n <= m) return fail(GS_EINVAL, w + ": need n > m samples");
+    if (ldx < m) return fail(GS_EINVAL, w + ": ldx < m");
+    if (reinterpret_cast<uintptr_t>(out) % 16 != 0)
+        return fail(GS_EINVAL, w + ": output must be 16-byte aligned");
+    return GS_OK;
+}
+
+// Enqueue R0 and the anchors; returns GS_OK or an error code.
+int front_half(gs_plan_s *p, const double *X, int64_t n, int m, int64_t ldx, hipStream_t s,
+               hipEvent_t *ev) {
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    hipLaunchKernelGGL(zero_status_kernel, dim3(1), dim3(64), 0, s, p->d_status);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "status reset launch");
+    if ((e = launch_qr_r0(X, n, m, ldx, p->d_r0, p->d_qr_a, p->d_qr_b, p->d_status, s)) != hipSuccess)
+        return hip_fail(e, "R0 QR launch");
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if ((e = launch_anchors(p->d_r0, p->m, p->k, p->ks, p->nseg, p->d_anchor, p->d_tail, s)) !=
+        hipSuccess)
+        return hip_fail(e, "anchor launch");
+    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return GS_OK;
+}
+
+hipEvent_t *new_event_set(gs_plan_s *p) {
+    if (!p->timing) return nullptr;
+    std::array<hipEvent_t, 4> ev{};
+    for (auto &x : ev)
+        if (hipEventCreate(&x) != hipSuccess) return nullptr;
+    p->events.push_back(ev);
+    return p->events.back().data();
+}
+
+template <typename T>
+int score_all_impl(gs_plan_s *p, const double *X, int64_t n, int m, int64_t ldx, T *scores,
+                   int what, void *stream, const char *who) {
+    int st = check_common(p, X, n, m, ldx, scores, who);
+    if (st != GS_OK) return st;
+    if (what != GS_OUT_BIC && what != GS_OUT_RSS)
+        return fail(GS_EINVAL, std::string(who) + ": what must be GS_OUT_BIC or GS_OUT_RSS");
+    if ((st = ensure_workspace(p, n)) != GS_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t *ev = new_event_set(p);
+    if ((st = front_half(p, X, n, m, ldx, s, ev)) != GS_OK) return st;
+    hipError_t e;
+    if constexpr (std::is_same_v<T, float>)
+        e = launch_walk_f32(p, p->d_anchor, p->d_tail, scores, n, what == GS_OUT_BIC, s);
+    else
+        e = launch_walk_f64(p, p->d_anchor, p->d_tail, scores, n, what == GS_OUT_BIC, s);
+    if (e != hipSuccess) return hip_fail(e, "walk launch");
+    if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    p->last_stream = s;
+    return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gs_plan_destroy(gs_plan_t *p) {
+    if (!p) return;
+    if (p->device >= 0) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(p->device);
+        if (p->done) (void)hipEventSynchronize(p->done);
+        free_device(p);
+        (void)hipSetDevice(cur);
+    }
+    delete p;
+}
+
+int gs_qr_r0(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx, double *R0,
+             void *stream) {
+    int st = check_common(p, X, n, m, ldx, R0, "gs_qr_r0");
+    if (st != GS_OK) return st;
+    if ((st = ensure_workspace(p, n)) != GS_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(zero_status_kernel, dim3(1), dim3(64), 0, s, p->d_status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "status reset launch");
+    if ((e = launch_qr_r0(X, n, m, ldx, R0, p->d_qr_a, p->d_qr_b, p->d_status, s)) != hipSuccess)
+        return hip_fail(e, "R0 QR launch");
+    if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return GS_OK;
+}
+
+int gs_score_all(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx, float *scores,
+                 int what, void *stream) {
+    return score_all_impl<float>(p, X, n, m, ldx, scores, what, stream, "gs_score_all");
+}
+
+int gs_score_all_f64(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx, double *scores,
+                     int what, void *stream) {
+    return score_all_impl<double>(p, X, n, m, ldx, scores, what, stream, "gs_score_all_f64");
+}
+
+int gs_sync_status(gs_plan_t *p) {
+    if (!p) return fail(GS_EINVAL, "gs_sync_status: plan is NULL");
+    if (p->device < 0) return GS_OK;
+    hipError_t e = hipEventSynchronize(p->done);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    int flags = 0;
+    if ((e = hipMemcpy(&flags, p->d_status, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "status copy");
+    if (flags & GS_FLAG_NOTFINITE) return fail(GS_ENOTFINITE, "X holds NaN or Inf");
+    if (flags & GS_FLAG_RANK) return fail(GS_ERANK, "X is rank deficient (R0 diagonal ~ 0)");
+    return GS_OK;
+}
+
+int gs_set_timing(gs_plan_t *p, int enable) {
+    if (!p) return fail(GS_EINVAL, "gs_set_timing: plan is NULL");
+    for (auto &ev : p->events) {
+        (void)hipEventSynchronize(ev[3]);
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    p->events.clear();
+    p->timing = enable != 0;
+    return GS_OK;
+}
+
+int gs_get_timing(gs_plan_t *p, double *ms, int64_t *count) {
+    if (!p || !ms || !count) return fail(GS_EINVAL, "gs_get_timing: NULL argument");
+    double acc[4] = {0, 0, 0, 0};
+    int64_t cnt = 0;
+    for (auto &ev : p->events) {
+        hipError_t e = hipEventSynchronize(ev[3]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+        if ((e = hipEventElapsedTime(&t01, ev[0], ev[1])) != hipSuccess ||
+            (e = hipEventElapsedTime(&t12, ev[1], ev[2])) != hipSuccess ||
+            (e = hipEventElapsedTime(&t23, ev[2], ev[3])) != hipSuccess ||
+            (e = hipEventElapsedTime(&t03, ev[0], ev[3])) != hipSuccess)
+            return hip_fail(e, "hipEventElapsedTime");
+        acc[0] += t01;
+        acc[1] += t12;
+        acc[2] += t23;
+        acc[3] += t03;
+        ++cnt;
+    }
+    for (int i = 0; i < 4; ++i) ms[i] = cnt ? acc[i] / double(cnt) : 0.0;
+    *count = cnt;
+    return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,381 @@
+// The walk: adjacent column swaps with one Givens retriangularisation each
+// (Sec. 1.3), along the shortest sequence of orderings (Sec. 3-4), split into
+// independent segments (Sec. 6), with every visited R turned into RSS and BIC
+// values of the families it solves (Sec. 2) and written to the score table.
+//
+// Mapping to the GPU (one 32-lane half of a wave per segment, two per wave):
+//   - lane l holds the column of one variable (lanes 0..ks-1 the inner block,
+//     ks..k-1 the middle variables, then the back variables).  A column swap is
+//     then only a relabelling; the Givens step mixes two rows in every lane.
+//   - the inner block's ks rows live in registers; the inner walk is unrolled at
+//     compile time, so each row index is a constant.  The q middle rows live in
+//     LDS, addressed at run time.
+//   - the pivot column's two entries are broadcast inside the half-wave with
+//     ds_bpermute.
+//   - each inner walk fills one table line (2^ks consecutive entries) per child
+//     column in registers; it is written out with 16-byte stores at its end.
+//
+// Givens step at rows (j, j+1) after exchanging the columns at positions j, j+1
+// (Sec. 1.3): with a = r[j][piv], b = r[j+1][piv] of the new column at j+1... the
+// pivot is the column that moves from j+1 to j, rho = sqrt(a^2 + b^2),
+// c = a / rho, s = b / rho.  The rows become
+//   r[j]   <- c r[j] + s r[j+1]
+//   r[j+1] <- s r[j] - c r[j+1],
+// the reflector form of the paper's rotation (it keeps the new diagonal entry
+// rho positive and differs from the rotation only by the sign of row j+1, which
+// no RSS depends on).  The pivot's new r[j+1] is set to exactly zero.  rho = 0
+// (a rank-deficient prefix) uses c = 1, s = 0.
+//
+// RSS from R (the paper names the models each QRD solves but not the formula):
+// for an ordering with variable c at position p, RSS(c | first i variables) is
+// the sum of the squares of column c over rows i..p.  Per lane the kernels keep
+// these suffix sums: after a swap at j only the one for row j+1 changes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <type_traits>
+
+#include "gs_internal.hpp"
+
+namespace gs {
+
+template <int I, int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+__device__ __forceinline__ float bcast(float v, int addr) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double bcast(double v, int addr) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, int(bits & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, int(bits >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned long long)(unsigned)lo));
+}
+
+template <typename T>
+struct Arith;
+
+template <>
+struct Arith<float> {
+    static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float tiny() { return 1.17549435e-38f; }
+    // BIC from RSS/n: n ln(RSS/n) + cst = (n ln 2) log2(RSS/n) + cst
+    static __device__ __forceinline__ float score(float rss, float nlog, float cst) {
+        return fmaf(nlog, __builtin_amdgcn_logf(rss), cst);
+    }
+};
+
+template <>
+struct Arith<double> {
+    static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+    static __device__ __forceinline__ double tiny() { return 2.2250738585072014e-308; }
+    static __device__ __forceinline__ double score(double rss, double nlog, double cst) {
+        return fma(nlog, log(rss), cst);
+    }
+};
+
+// c, s of the step from the pivot's entries (a, b) at rows j, j+1.
+template <typename T>
+__device__ __forceinline__ void givens_cs(T a, T b, T &c, T &s) {
+    const T rr = a * a + b * b;
+    const T r = Arith<T>::rsq(rr > Arith<T>::tiny() ? rr : Arith<T>::tiny());
+    c = rr > T(0) ? a * r : T(1);
+    s = b * r;
+}
+
+struct WalkArgs {
+    int m, k, q;
+    int64_t nseg, nsub;
+    double row_scale;  // 1/sqrt(n) for BIC (the table then gets RSS/n inside the log), 1 for RSS
+    double nlog;       // n ln 2 (FP32 path, log2 in hardware) or n (FP64 path)
+    double lnn;        // ln n
+};
+
+template <int CNT, typename T>
+__device__ __forceinline__ void store_line(T *dst, const T *v) {
+    constexpr int VE = 16 / int(sizeof(T));
+    if constexpr (CNT % VE == 0) {
+        using V = std::conditional_t<std::is_same_v<T, float>, float4, double2>;
+        static_for<0, CNT / VE>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            V w;
+            if constexpr (std::is_same_v<T, float>) {
+                w.x = v[4 * i + 0];
+                w.y = v[4 * i + 1];
+                w.z = v[4 * i + 2];
+                w.w = v[4 * i + 3];
+            } else {
+                w.x = v[2 * i + 0];
+                w.y = v[2 * i + 1];
+            }
+            reinterpret_cast<V *>(dst)[i] = w;
+        });
+    } else {
+        static_for<0, CNT>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            dst[i] = v[i];
+        });
+    }
+}
+
+// v_cndmask with a wave-uniform lane mask: lanes whose bit is set take `set`.
+// Written as one instruction so that the compiler cannot turn a choice between two
+// register-array elements into a run-time index into that array.
+__device__ __forceinline__ float select_lanes(uint64_t mask, float set, float other) {
+    float r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(other), "v"(set), "s"(mask));
+    return r;
+}
+__device__ __forceinline__ double select_lanes(uint64_t mask, double set, double other) {
+    const long long s = __double_as_longlong(set), o = __double_as_longlong(other);
+    int lo, hi;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3"
+                 : "=v"(lo) : "v"(int(o & 0xffffffffll)), "v"(int(s & 0xffffffffll)), "s"(mask));
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3"
+                 : "=v"(hi) : "v"(int(o >> 32)), "v"(int(s >> 32)), "s"(mask));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned long long)(unsigned)lo));
+}
+
+// insert a zero bit at position c of i
+__host__ __device__ constexpr int expand_bit(int i, int c) {
+    return ((i >> c) << (c + 1)) | (i & ((1 << c) - 1));
+}
+
+constexpr int WALK_WAVES = 4;  // waves per workgroup (8 segments)
+
+template <typename T, int KS, bool BIC>
+__global__ __launch_bounds__(64 * WALK_WAVES) void walk_kernel(const double *__restrict__ anchor,
+                                                              const double *__restrict__ tail,
+                                                              const uint32_t *__restrict__ prog,
+                                                              T *__restrict__ out, WalkArgs a) {
+    constexpr int N = InnerProgram<KS>::N;
+    constexpr int NS = 1 << KS;
+    __shared__ T Lrows[WALK_WAVES][Q_MAX][64];
+
+    const int wave = threadIdx.x >> 6;
+    const int lane64 = threadIdx.x & 63;
+    const int half = lane64 >> 5;
+    const int lane = lane64 & 31;
+    const int64_t seg = (int64_t(blockIdx.x) * WALK_WAVES + wave) * 2 + half;
+    const bool seg_ok = seg < a.nseg;
+    const int m = a.m, k = a.k, q = a.q, nout = m - k;
+    const int bbase = half * 128;  // ds_bpermute byte address of lane 0 of this half
+    T(*L)[64] = Lrows[wave];
+
+    // lane -> variable label and class: 1 inner, 2 middle, 3 back, 0 unused
+    const uint64_t scode = seg_ok ? uint64_t(seg) : 0;
+    int label = -1, cls = 0;
+    if (lane < KS) {
+        label = lane;
+        cls = 1;
+    } else if (lane < k) {
+        label = lane;
+        cls = 2;
+    } else {
+        int cnt = 0;
+        for (int b = 0; b < nout; ++b)
+            if (!((scode >> b) & 1)) {
+                if (cnt == lane - k) {
+                    label = k + b;
+                    cls = 3;
+                }
+                ++cnt;
+            }
+    }
+    if (!seg_ok) cls = 0;
+    const uint64_t Fbits = scode << k;
+    const int nF = __popcll((unsigned long long)scode);
+
+    // anchor (FP64) -> working precision
+    const double rs = a.row_scale;
+    const int64_t sidx = seg_ok ? seg : 0;
+    const double *an = anchor + sidx * int64_t(k) * 32;
+    T I[KS];
+#pragma unroll
+    for (int i = 0; i < KS; ++i) I[i] = seg_ok ? T(an[(q + i) * 32 + lane] * rs) : T(0);
+    for (int p = 0; p < q; ++p) L[p][lane64] = seg_ok ? T(an[p * 32 + lane] * rs) : T(0);
+    const T tl = seg_ok ? T(tail[sidx * 32 + lane] * rs * rs) : T(0);
+    const T nlog = T(a.nlog), lnn = T(a.lnn);
+
+    int z = q;
+    for (int64_t t = 0; t < a.nsub; ++t) {
+        const uint32_t w0 = prog[2 * t], w1 = prog[2 * t + 1];
+        const bool fwd = (t & 1) == 0;
+        if (w1 & SubWord::kHasTransition) {
+            if (w1 & SubWord::kHasMid) {
+                // swap of two middle variables on the same side of the inner block
+                const int j = int((w1 >> 2) & 31), piv = int((w1 >> 8) & 31);
+                const int addr = bbase + piv * 4;
+                T x = L[j][lane64], y = L[j + 1][lane64];
+                T c, s;
+                givens_cs(bcast(x, addr), bcast(y, addr), c, s);
+                const T nx = c * x + s * y;
+                T ny = s * x - c * y;
+                if (lane == piv) ny = T(0);
+                L[j][lane64] = nx;
+                L[j + 1][lane64] = ny;
+            }
+            const int v = int((w1 >> 16) & 31);
+            if (w1 & SubWord::kCrossLeft) {
+                // middle variable v (first behind the inner block) moves to its front
+                T carry = L[z][lane64];
+                const int addr = bbase + v * 4;
+                static_for<0, KS>([&](auto ic) {
+                    constexpr int i = KS - 1 - decltype(ic)::value;
+                    T c, s;
+                    givens_cs(bcast(I[i], addr), bcast(carry, addr), c, s);
+                    const T top = c * I[i] + s * carry;
+                    T bot = s * I[i] - c * carry;
+                    if (lane == v) bot = T(0);
+                    I[i] = bot;
+                    carry = top;
+                });
+                L[z][lane64] = carry;
+                ++z;
+            } else {
+                // the last front middle variable moves behind the inner block
+                T carry = L[z - 1][lane64];
+                static_for<0, KS>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    const int piv = fwd ? kInner<KS>.order_f[i] : kInner<KS>.order_r[i];
+                    const int addr = bbase + piv * 4;
+                    T c, s;
+                    givens_cs(bcast(carry, addr), bcast(I[i], addr), c, s);
+                    const T top = c * carry + s * I[i];
+                    T bot = s * carry - c * I[i];
+                    if (lane == piv) bot = T(0);
+                    I[i] = top;
+                    carry = bot;
+                });
+                L[z - 1][lane64] = carry;
+                --z;
+            }
+        }
+
+        const uint32_t omask = w0 & 0xFFFFu;
+        // suffix sums below the inner block: middle rows behind it and the back rows
+        T base = tl;
+        for (int p = q - 1; p >= z; --p) {
+            const T r = L[p][lane64];
+            base = r * r + base;
+        }
+        T sfx[KS + 1];
+        sfx[KS] = base;
+#pragma unroll
+        for (int i = KS - 1; i >= 0; --i) sfx[i] = I[i] * I[i] + sfx[i + 1];
+        T cst[KS + 1];
+        const int cnt0 = nF + __popc(omask) + 2;
+#pragma unroll
+        for (int u = 0; u <= KS; ++u) cst[u] = T(cnt0 + u) * lnn;
+
+        T o[NS];
+        auto score = [&](T rss, int u) -> T {
+            if constexpr (BIC) return Arith<T>::score(rss, nlog, cst[u]);
+            else return rss;
+        };
+        auto inner_walk = [&](auto dirc) {
+            constexpr bool FWD = decltype(dirc)::value;
+            static_for<0, KS + 1>([&](auto pc) {
+                constexpr int pl = decltype(pc)::value;
+                constexpr int U = FWD ? kInner<KS>.init_f[pl] : kInner<KS>.init_r[pl];
+                o[U] = score(sfx[pl], popcount_c(U));
+            });
+            static_for<0, N>([&](auto sc) {
+                constexpr int st = decltype(sc)::value;
+                constexpr int J = FWD ? kInner<KS>.j_f[st] : kInner<KS>.j_r[st];
+                constexpr int PV = FWD ? kInner<KS>.piv_f[st] : kInner<KS>.piv_r[st];
+                constexpr int U = FWD ? kInner<KS>.mask_f[st] : kInner<KS>.mask_r[st];
+                const int addr = bbase + PV * 4;
+                T c, s;
+                givens_cs(bcast(I[J], addr), bcast(I[J + 1], addr), c, s);
+                const T x = I[J], y = I[J + 1];
+                I[J] = c * x + s * y;
+                T ny = s * x - c * y;
+                if (lane == PV) ny = T(0);
+                I[J + 1] = ny;
+                sfx[J + 1] = ny * ny + sfx[J + 2];
+                o[U] = score(sfx[J + 1], popcount_c(U));
+            });
+        };
+        if (fwd) inner_walk(std::true_type{});
+        else inner_walk(std::false_type{});
+
+        // write this sub-walk's table lines
+        const uint64_t Shi = Fbits | (uint64_t(omask) << KS);
+        const int64_t cbase = int64_t(label) << (m - 1);
+        if (cls == 1) {
+            constexpr int NH = NS / 2;
+            T h[NH];
+            static_for<0, NH>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                T val = o[expand_bit(i, 0)];
+                static_for<1, KS>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    constexpr uint64_t lanes = (uint64_t(1) << c) | (uint64_t(1) << (32 + c));
+                    val = select_lanes(lanes, o[expand_bit(i, c)], val);
+                });
+                h[i] = val;
+            });
+            store_line<NH>(out + cbase + int64_t(Shi >> 1), h);
+        } else if (cls == 3 || (cls == 2 && !((omask >> (lane - KS)) & 1u))) {
+            const uint64_t low = Shi & ((uint64_t(1) << label) - 1);
+            const uint64_t high = (Shi >> (label + 1)) << label;
+            store_line<NS>(out + cbase + int64_t(low | high), o);
+        }
+    }
+}
+
+template <typename T, bool BIC>
+static hipError_t launch_walk_t(const gs_plan_s *p, const double *anchor, const double *tail,
+                                T *out, int64_t n, hipStream_t s) {
+    WalkArgs a;
+    a.m = p->m;
+    a.k = p->k;
+    a.q = p->q;
+    a.nseg = p->nseg;
+    a.nsub = p->nsub;
+    const double dn = double(n);
+    a.row_scale = BIC ? 1.0 / std::sqrt(dn) : 1.0;
+    a.nlog = std::is_same_v<T, float> ? dn * 0.6931471805599453 : dn;
+    a.lnn = std::log(dn);
+    const int64_t segs_per_block = 2 * WALK_WAVES;
+    const dim3 grid(unsigned((p->nseg + segs_per_block - 1) / segs_per_block));
+    const dim3 block(64 * WALK_WAVES);
+    switch (p->ks) {
+#define GS_WALK_CASE(KSV)                                                                   \
+    case KSV:                                                                               \
+        hipLaunchKernelGGL((walk_kernel<T, KSV, BIC>), grid, block, 0, s, anchor, tail,    \
+                           p->d_prog, out, a);                                              \
+        break;
+        GS_WALK_CASE(1)
+        GS_WALK_CASE(2)
+        GS_WALK_CASE(3)
+        GS_WALK_CASE(4)
+        GS_WALK_CASE(5)
+        GS_WALK_CASE(6)
+#undef GS_WALK_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_f32(const gs_plan_s *p, const double *anchor, const double *tail, float *out,
+                           int64_t n, bool bic, hipStream_t s) {
+    return bic ? launch_walk_t<float, true>(p, anchor, tail, out, n, s)
+               : launch_walk_t<float, false>(p, anchor, tail, out, n, s);
+}
+
+hipError_t launch_walk_f64(const gs_plan_s *p, const double *anchor, const double *tail,
+                           double *out, int64_t n, bool bic, hipStream_t s) {
+    return bic ? launch_walk_t<double, true>(p, anchor, tail, out, n, s)
+               : launch_walk_t<double, false>(p, anchor, tail, out, n, s);
+}
+
+}  // namespace gs

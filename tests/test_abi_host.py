@@ -1,0 +1,109 @@
+"""Host-side checks of libgivscore (no GPU needed): the library loads, exports every
+symbol its header declares, validates arguments before touching the device, and its
+integer planner covers every family exactly once."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import walk as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def gs():
+    import paper_1901_07643_amd as g
+    g.lib()
+    return g
+
+
+def test_header_symbols_exported(gs):
+    hdr = open(os.path.join(ROOT, "include", "givscore.h")).read()
+    names = set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(gs_\w+)\s*\(", hdr, re.M))
+    assert {"gs_plan", "gs_score_all", "gs_score_all_f64", "gs_qr_r0"} <= names
+    L = ctypes.CDLL(gs._abi.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(L, n), f"{n} declared in the header but not exported"
+
+
+def test_family_index_matches_oracle(gs):
+    rng = np.random.default_rng(0)
+    for m in [1, 2, 5, 13, 26, 30]:
+        for _ in range(200):
+            c = int(rng.integers(0, m))
+            mask = int(rng.integers(0, 1 << m)) & ~(1 << c)
+            assert gs.family_index(m, c, mask) == oracle.family_index(m, c, mask)
+        assert gs.num_families(m) == m * 2 ** (m - 1)
+    with pytest.raises(gs.GivScoreError):
+        gs.family_index(5, 2, 0b100)
+    with pytest.raises(gs.GivScoreError):
+        gs.num_families(31)
+
+
+@pytest.mark.parametrize("m", range(1, 15))
+def test_upsilon_matches_reference(gs, m):
+    assert gs.upsilon(m) == W.greedy_swaps(m)
+
+
+def test_plan_argument_errors(gs):
+    with pytest.raises(gs.GivScoreError) as e:
+        gs.Plan(0)
+    assert e.value.code == gs.GS_EINVAL
+    for m, k, ks in [(31, 0, 0), (10, 3, 5), (10, 11, 5), (30, 30, 5), (8, 8, 7)]:
+        with pytest.raises(gs.GivScoreError):
+            gs.Plan(m, k, ks)
+
+
+def test_score_argument_errors_before_device_work(gs):
+    L = gs.lib()
+    p = gs.Plan(6)
+    fake = ctypes.c_void_p(4096)
+    # n <= m, ldx < m, m mismatch, bad output selector, misaligned output, NULL data
+    assert L.gs_score_all(p.handle, fake, 6, 6, 6, fake, 0, None) == gs.GS_EINVAL
+    assert L.gs_score_all(p.handle, fake, 50, 6, 5, fake, 0, None) == gs.GS_EINVAL
+    assert L.gs_score_all(p.handle, fake, 50, 7, 7, fake, 0, None) == gs.GS_EINVAL
+    assert L.gs_score_all(p.handle, fake, 50, 6, 6, fake, 7, None) == gs.GS_EINVAL
+    assert L.gs_score_all(p.handle, fake, 50, 6, 6, ctypes.c_void_p(4100), 0, None) == gs.GS_EINVAL
+    assert L.gs_score_all_f64(p.handle, None, 50, 6, 6, fake, 0, None) == gs.GS_EINVAL
+    assert L.gs_qr_r0(None, fake, 50, 6, 6, fake, None) == gs.GS_EINVAL
+    assert "plan" in gs.last_error()
+
+
+def _plans():
+    out = []
+    for m in range(1, 15):
+        for ks in range(1, min(6, m) + 1):
+            for k in sorted({ks, min(m, ks + 1), min(m, ks + 3), m}):
+                if k - ks <= 16:
+                    out.append((m, k, ks))
+    return out
+
+
+@pytest.mark.parametrize("m,k,ks", _plans())
+def test_plan_covers_every_family_once(gs, m, k, ks):
+    p = gs.Plan(m, k, ks)
+    info = p.info
+    q = k - ks
+    assert info["num_segments"] == 2 ** (m - k) and info["sub_per_segment"] == 2 ** q
+    # Givens steps of the two-level walk = the optimum 2^k - k - 1 of one segment
+    steps = (2 ** q - 1) * ks + (2 ** q - q - 1) + 2 ** q * W.swap_count(ks)
+    assert steps == info["swaps_per_segment"] == W.swap_count(k)
+    c = p.count_emissions()
+    assert c.size == m * 2 ** (m - 1) and (c == 1).all()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("m,k,ks", [(18, 13, 5), (20, 7, 5), (16, 16, 6), (22, 9, 5)])
+def test_plan_covers_every_family_once_large(gs, m, k, ks):
+    c = gs.Plan(m, k, ks).count_emissions()
+    assert (c == 1).all()
+
+
+def test_default_plans(gs):
+    for m, k, ks in [(8, 5, 5), (14, 5, 5), (20, 7, 5), (26, 13, 5), (30, 17, 5), (3, 3, 3)]:
+        inf = gs.Plan(m).info
+        assert (inf["k"], inf["ks"]) == (k, ks)

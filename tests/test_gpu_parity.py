@@ -1,0 +1,241 @@
+"""GPU parity of the HIP walk against the FP64 CPU oracle (marked gpu).
+
+Every comparison is element by element on the same seeded inputs: the whole table
+where the oracle finishes in seconds, sampled table indices at the full sizes (the
+m = 26, n = 5000 workload is run with the default plan, the launch configuration
+the benchmark times).  The table is pre-filled with NaN so that an entry the
+kernels never write fails the check.
+
+Tolerances (relative RSS error against the FP64 oracle):
+  FP64 walk: 1e-10;  FP32 walk (FP64 segment starts): 1e-4.
+BIC = n ln(RSS/n) + (|S|+2) ln n moves by n ln(1 + tol) for a relative RSS error tol,
+plus the rounding of the BIC value itself:
+  |dBIC| <= n * tol + 8 * eps * |BIC| + n * ln2 * 2^-21 (FP32 hardware log2).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from datagen import CONFIGS, config_data, linear_gaussian
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def gs():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1901_07643_amd as g
+    g.lib()
+    return g
+
+
+def _run(gs, X, what, precision, plan=None):
+    Xd = torch.as_tensor(X, device="cuda")
+    m = X.shape[1]
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    out = torch.full((gs.num_families(m),), float("nan"), dtype=dt, device="cuda")
+    gs.score_all(Xd, plan=plan, what=what, precision=precision, out=out)
+    torch.cuda.synchronize()
+    return out
+
+
+def _assert_rss(got, want, tol, label=""):
+    got = np.asarray(got, dtype=np.float64)
+    assert np.isfinite(got).all(), f"{label}: unwritten or non-finite entries"
+    rel = np.abs(got - want) / want
+    worst = int(np.argmax(rel))
+    assert rel.max() <= tol, f"{label}: max rel RSS err {rel.max():.3e} at {worst}"
+    return float(rel.max())
+
+
+def _bic_tol(n, bic, precision):
+    eps = 2.0 ** -23 if precision == "fp32" else 2.0 ** -52
+    t = n * TOL[precision] + 8 * eps * np.abs(bic)
+    if precision == "fp32":
+        t = t + n * math.log(2) * 2.0 ** -21
+    return t
+
+
+def _assert_bic(got, want, n, precision, label=""):
+    got = np.asarray(got, dtype=np.float64)
+    assert np.isfinite(got).all(), f"{label}: unwritten or non-finite entries"
+    err = np.abs(got - want)
+    tol = _bic_tol(n, want, precision)
+    bad = np.nonzero(err > tol)[0]
+    assert bad.size == 0, f"{label}: {bad.size} BIC entries off, first {bad[:5]} err {err[bad[:5]]}"
+
+
+# ---------------------------------------------------------------- R0
+
+@pytest.mark.parametrize("m,n", [(8, 200), (26, 5000), (5, 129), (30, 257)])
+def test_r0(gs, m, n):
+    X = linear_gaussian(m, n, 0.3, 0.5, 1.5, seed=m * 1000 + n)
+    R = gs.qr_r0(torch.as_tensor(X, device="cuda")).cpu().numpy()
+    assert np.array_equal(R, np.triu(R)) and (np.diag(R) >= 0).all()
+    # r_jj^2 is the RSS of variable j on the variables before it (Sec. 2)
+    want = np.array([oracle.rss(X, j, (1 << j) - 1) for j in range(m)])
+    _assert_rss(np.diag(R) ** 2, want, 1e-11, "diag")
+    G = X.T @ X
+    assert np.abs(R.T @ R - G).max() <= 1e-12 * np.abs(G).max()
+
+
+# ---------------------------------------------------------------- whole tables
+
+def test_c1_all_families(gs):
+    c = CONFIGS["c1_m8_n200"]
+    X = config_data("c1_m8_n200")
+    ref_rss = oracle.score_all(X, oracle.OUT_RSS)
+    ref_bic = oracle.score_all(X, oracle.OUT_BIC)
+    for prec in ("fp64", "fp32"):
+        got = _run(gs, X, "rss", prec).cpu().numpy()
+        _assert_rss(got, ref_rss, TOL[prec], f"C1 rss {prec}")
+        got = _run(gs, X, "bic", prec).cpu().numpy()
+        _assert_bic(got, ref_bic, c.n, prec, f"C1 bic {prec}")
+
+
+# (m, n, k, ks): plans that exercise one segment, many segments, middle blocks with
+# every inner size, inactive half-waves, a lone segment and ragged row blocks.
+WHOLE = [
+    (1, 5, 0, 0), (2, 7, 0, 0), (3, 9, 0, 0), (4, 40, 4, 2), (5, 33, 5, 1), (6, 50, 0, 0),
+    (7, 129, 7, 3), (8, 300, 8, 6), (9, 100, 9, 4), (10, 257, 10, 5), (11, 64, 8, 3),
+    (12, 200, 12, 6), (12, 130, 9, 5), (13, 100, 13, 2), (14, 500, 11, 5), (14, 500, 0, 0),
+]
+
+
+@pytest.mark.parametrize("m,n,k,ks", WHOLE)
+def test_whole_table(gs, m, n, k, ks):
+    X = linear_gaussian(m, n, 0.25, 0.5, 1.5, seed=17 + 31 * m + n)
+    plan = gs.Plan(m, k, ks)
+    ref_rss = oracle.score_all(X, oracle.OUT_RSS)
+    ref_bic = oracle.score_all(X, oracle.OUT_BIC)
+    for prec in ("fp64", "fp32"):
+        got = _run(gs, X, "rss", prec, plan).cpu().numpy()
+        _assert_rss(got, ref_rss, TOL[prec], f"m={m} rss {prec}")
+        got = _run(gs, X, "bic", prec, plan).cpu().numpy()
+        _assert_bic(got, ref_bic, n, prec, f"m={m} bic {prec}")
+
+
+# ---------------------------------------------------------------- full sizes, sampled
+
+def _sample(m, count, seed):
+    rng = np.random.default_rng(seed)
+    N = m * 2 ** (m - 1)
+    idx = rng.choice(N, size=count, replace=False)
+    return np.unique(np.concatenate([idx, [0, N - 1, N // 2, 2 ** (m - 1) - 1]])).astype(np.int64)
+
+
+@pytest.mark.parametrize("name", ["c2_m20_n1000", "c3_m26_n5000"])
+def test_full_size_sampled(gs, name):
+    c = CONFIGS[name]
+    X = config_data(name)
+    idx = _sample(c.m, 4096, c.seed)
+    ref_rss = oracle.score_indices(X, idx, oracle.OUT_RSS)
+    ref_bic = oracle.score_indices(X, idx, oracle.OUT_BIC)
+    it = torch.as_tensor(idx, device="cuda")
+    for prec in ("fp32", "fp64"):
+        out = _run(gs, X, "rss", prec)
+        assert not torch.isnan(out).any().item(), f"{name} {prec}: unwritten entries"
+        _assert_rss(out[it].cpu().numpy(), ref_rss, TOL[prec], f"{name} rss {prec}")
+        del out
+        out = _run(gs, X, "bic", prec)
+        assert not torch.isnan(out).any().item(), f"{name} {prec}: unwritten entries"
+        _assert_bic(out[it].cpu().numpy(), ref_bic, c.n, prec, f"{name} bic {prec}")
+        del out
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", ["c2_m20_n1000", "c3_m26_n5000"])
+def test_fp32_walk_vs_fp64_walk_whole_table(gs, name):
+    """Every entry of the FP32 walk against the FP64 walk of the same plan (the FP64
+    walk is itself pinned to the oracle above and in the whole-table tests)."""
+    X = config_data(name)
+    a = _run(gs, X, "rss", "fp32")
+    b = _run(gs, X, "rss", "fp64")
+    worst = 0.0
+    for lo in range(0, a.numel(), 1 << 27):
+        hi = min(a.numel(), lo + (1 << 27))
+        rel = ((a[lo:hi].double() - b[lo:hi]).abs() / b[lo:hi]).max().item()
+        worst = max(worst, rel)
+    print(f"\n{name}: max rel RSS err FP32 walk vs FP64 walk = {worst:.3e}")
+    assert worst <= TOL["fp32"]
+
+
+def test_max_m(gs):
+    """m = 30, the largest supported size (64 GB FP32 table), sampled."""
+    m, n = 30, 48
+    X = linear_gaussian(m, n, 0.1, 0.3, 1.0, seed=30)
+    idx = _sample(m, 1024, 30)
+    ref = oracle.score_indices(X, idx, oracle.OUT_RSS)
+    out = _run(gs, X, "rss", "fp32")
+    for lo in range(0, out.numel(), 1 << 30):
+        assert not torch.isnan(out[lo:lo + (1 << 30)]).any().item()
+    _assert_rss(out[torch.as_tensor(idx, device="cuda")].cpu().numpy(), ref, TOL["fp32"], "m=30")
+    del out
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_strided_rows(gs):
+    m, n = 9, 77
+    Xw = linear_gaussian(m + 4, n, 0.3, 0.5, 1.5, seed=4)
+    X = Xw[:, :m]
+    Xd = torch.as_tensor(Xw, device="cuda")[:, :m]
+    assert Xd.stride(0) == m + 4
+    ref = oracle.score_all(np.ascontiguousarray(X), oracle.OUT_RSS)
+    out = gs.score_all(Xd, what="rss", precision="fp64").cpu().numpy()
+    _assert_rss(out, ref, TOL["fp64"], "strided")
+
+
+def test_minimal_samples(gs):
+    m = 10
+    X = linear_gaussian(m, m + 1, 0.3, 0.5, 1.5, seed=5)
+    ref = oracle.score_all(X, oracle.OUT_RSS)
+    out = gs.score_all(torch.as_tensor(X, device="cuda"), what="rss", precision="fp64").cpu().numpy()
+    _assert_rss(out, ref, 1e-8, "n=m+1")
+
+
+def test_nonfinite_and_rank_status(gs):
+    X = linear_gaussian(6, 40, 0.3, 0.5, 1.5, seed=6)
+    Xn = X.copy()
+    Xn[3, 2] = np.nan
+    with pytest.raises(gs.GivScoreError) as e:
+        gs.score_all(torch.as_tensor(Xn, device="cuda"))
+    assert e.value.code == gs.GS_ENOTFINITE
+    Xr = X.copy()
+    Xr[:, 4] = Xr[:, 1]
+    plan = gs.Plan(6)
+    out = gs.score_all(torch.as_tensor(Xr, device="cuda"), plan=plan, what="rss",
+                       precision="fp64", check_status=False)
+    assert plan.status() == gs.GS_ERANK
+    # families that do not hold both copies of the duplicated column are unaffected
+    ref = oracle.score_all(Xr, oracle.OUT_RSS)
+    keep = []
+    for i in range(ref.size):
+        c, mask = oracle.family_decode(6, i)
+        allv = mask | (1 << c)
+        if not ((allv >> 1) & 1 and (allv >> 4) & 1):
+            keep.append(i)
+    keep = np.array(keep)
+    got = out.cpu().numpy()
+    assert np.isfinite(got).all()
+    _assert_rss(got[keep], ref[keep], 1e-8, "rank-deficient")
+    # a clean call afterwards reports OK again
+    gs.score_all(torch.as_tensor(X, device="cuda"), plan=plan)
+    assert plan.status() == gs.GS_OK
+
+
+def test_deterministic_and_timing(gs):
+    X = config_data("c2_m20_n1000")
+    plan = gs.Plan(20)
+    plan.set_timing(True)
+    a = _run(gs, X, "bic", "fp32", plan)
+    b = _run(gs, X, "bic", "fp32", plan)
+    assert torch.equal(a, b)
+    ms, cnt = plan.timing()
+    assert cnt == 2 and all(x > 0 for x in ms) and ms[3] >= ms[2]
