@@ -27,6 +27,8 @@
 
 namespace gs {
 
+constexpr int kDefaultMaxK = 13;
+
 static thread_local std::string g_err;
 
 void set_error(const std::string &msg) { g_err = msg; }
@@ -230,9 +232,12 @@ int gs_plan_tuned(int m, int k, int ks, gs_plan_t **out) {
     if (m < 1 || m > GS_MAX_M) return fail(GS_EINVAL, "gs_plan: m must be in 1..30");
     if (ks == 0) ks = m < 5 ? m : 5;
     if (k == 0) {
+        // at least 2^13 segments when m allows (enough half-waves to fill the chip),
+        // and at most 2^13 - 14 Givens steps per segment: the FP32 walk's rounding
+        // error grows with the length of the walk from its FP64 start
         k = m - 13;
+        if (k > kDefaultMaxK) k = kDefaultMaxK;
         if (k < ks) k = ks;
-        if (k > ks + Q_MAX) k = ks + Q_MAX;
     }
     if (ks < 1 || ks > KS_MAX || ks > m) return fail(GS_EINVAL, "gs_plan: ks must be in 1..min(6,m)");
     if (k < ks || k > m || k - ks > Q_MAX)

@@ -63,7 +63,17 @@ struct Arith;
 
 template <>
 struct Arith<float> {
+#ifndef GS_RSQ_RAW
+    // hardware 1/sqrt plus one Newton step, so that c^2 + s^2 = 1 to rounding:
+    // a biased normalisation error would scale the rows a little at every step
+    static __device__ __forceinline__ float rsq(float x) {
+        const float y = __builtin_amdgcn_rsqf(x);
+        const float r = fmaf(-x * y, y, 1.0f);
+        return fmaf(0.5f * y, r, y);
+    }
+#else
     static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+#endif
     static __device__ __forceinline__ float tiny() { return 1.17549435e-38f; }
     // BIC from RSS/n: n ln(RSS/n) + cst = (n ln 2) log2(RSS/n) + cst
     static __device__ __forceinline__ float score(float rss, float nlog, float cst) {
