@@ -72,6 +72,7 @@ typedef struct {
     int64_t sub_per_segment;    /* 2^q inner walks per segment                        */
     int64_t swaps_per_segment;  /* Givens steps per segment: 2^k - k - 1              */
     int64_t num_families;       /* m * 2^(m-1)                                        */
+    int64_t num_waves;          /* 64-lane waves the segments are packed into         */
 } gs_plan_info_t;
 
 /* Number of families m * 2^(m-1); -1 if m is outside 1..GS_MAX_M. */

@@ -28,6 +28,7 @@ class PlanInfo(ctypes.Structure):
         ("m", ctypes.c_int), ("k", ctypes.c_int), ("ks", ctypes.c_int), ("q", ctypes.c_int),
         ("num_segments", ctypes.c_int64), ("sub_per_segment", ctypes.c_int64),
         ("swaps_per_segment", ctypes.c_int64), ("num_families", ctypes.c_int64),
+        ("num_waves", ctypes.c_int64),
     ]
 
 

@@ -8,90 +8,165 @@
 // rows of the back variables never change either and only enter through their
 // squared sums (the "tail" of each back column).
 //
-// Output layout, per segment s, in "lane" order (lane l < k holds the column of
-// variable l, lane k + i the i-th back variable in ascending label order):
+// One 32-lane half-wave per segment; lane c holds column c of R0 P in registers
+// (rows 0..MM-1, MM >= m, zero below m).  Each Householder step broadcasts the
+// pivot column through LDS and updates every column at once.
+//
+// Output layout, per segment s, by column slot l (l < k: variable l; l = k + i:
+// the i-th back variable in ascending label order):
 //   anchor[s][r][l], r = 0..k-1 local rows (first the q middle rows, then the ks
 //                    inner rows), l = 0..31
 //   tail[s][l]     = sum of squares of column l over the back rows.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "gs_internal.hpp"
 
 namespace gs {
 
-__global__ __launch_bounds__(64) void anchor_kernel(const double *__restrict__ R0, int m, int k,
-                                                    int ks, int64_t nseg,
-                                                    double *__restrict__ anchor,
-                                                    double *__restrict__ tail) {
-    __shared__ double A[32][33];
-    __shared__ int pos_label[32];
-    const int64_t seg = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int q = k - ks, nout = m - k;
-    if (seg >= nseg) return;
-    const int d = __popcll((unsigned long long)seg);
-    if (lane == 0) {
-        int pos = 0;
-        for (int b = nout - 1; b >= 0; --b)
-            if ((seg >> b) & 1) pos_label[pos++] = k + b;  // front, descending labels
-        for (int p = 0; p < q; ++p) pos_label[pos++] = ks + p;  // middle
-        for (int i = 0; i < ks; ++i) pos_label[pos++] = i;      // inner
-        for (int b = 0; b < nout; ++b)
-            if (!((seg >> b) & 1)) pos_label[pos++] = k + b;  // back, ascending
+template <int I, int N, typename Fn>
+__device__ __forceinline__ void static_for_a(Fn &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for_a<I + 1, N>(f);
     }
-    __syncthreads();
-    for (int e = lane; e < m * m; e += 64) {
-        const int r = e / m, c = e - (e / m) * m;
-        A[r][c] = R0[r * m + pos_label[c]];
-    }
-    __syncthreads();
-    // Householder QR of R0 P, one column per lane.
-    for (int j = 0; j < m; ++j) {
-        const double a = A[j][j];
-        double tailn = 0.0;
-        for (int i = j + 1; i < m; ++i) tailn += A[i][j] * A[i][j];
-        const double normx2 = tailn + a * a;
-        double alpha = a;
-        if (normx2 > 0.0) {
-            const double nrm = sqrt(normx2);
-            alpha = a >= 0.0 ? -nrm : nrm;
-            const double v0 = a - alpha;
-            const double vtv = tailn + v0 * v0;
-            if (lane > j && lane < m) {
-                double dot = v0 * A[j][lane];
-                for (int i = j + 1; i < m; ++i) dot += A[i][j] * A[i][lane];
-                const double f = 2.0 * dot / vtv;
-                A[j][lane] -= f * v0;
-                for (int i = j + 1; i < m; ++i) A[i][lane] -= f * A[i][j];
-            }
-        }
-        __syncthreads();
-        if (lane == j) {
-            A[j][j] = alpha;
-            for (int i = j + 1; i < m; ++i) A[i][j] = 0.0;
-        }
-        __syncthreads();
-    }
-    if (lane >= 32) return;
-    int pos = -1;
-    if (lane < ks) pos = d + q + lane;
-    else if (lane < k) pos = d + (lane - ks);
-    else if (lane < k + (nout - d)) pos = d + lane;  // back variables follow the k walked ones
-    double *an = anchor + seg * int64_t(k) * 32;
-    for (int r = 0; r < k; ++r) an[r * 32 + lane] = pos >= 0 ? A[d + r][pos] : 0.0;
-    double t = 0.0;
-    if (pos >= 0)
-        for (int r = d + k; r < m; ++r) t += A[r][pos] * A[r][pos];
-    tail[seg * 32 + lane] = t;
 }
 
-hipError_t launch_anchors(const double *R0, int m, int k, int ks, int64_t nseg, double *anchor,
-                          double *tail, hipStream_t s) {
-    hipLaunchKernelGGL(anchor_kernel, dim3(unsigned(nseg)), dim3(64), 0, s, R0, m, k, ks, nseg,
-                       anchor, tail);
+constexpr int ANCHOR_HALVES = 8;  // segments per 256-thread workgroup
+
+// Order LDS accesses of one wave: lane j writes the pivot column, the others read
+// it.  Without this the compiler may treat the cross-lane exchange as a data race
+// and move the reads ahead of the write.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int MM, typename TO>
+__global__ __launch_bounds__(256) void anchor_kernel(const double *__restrict__ R0, int m, int k,
+                                                     int ks, int64_t nseg, TO *__restrict__ anchor,
+                                                     TO *__restrict__ tail) {
+    __shared__ double piv_col[ANCHOR_HALVES][MM];
+    const int hw = threadIdx.x >> 5;
+    const int c = threadIdx.x & 31;
+    const int64_t seg = int64_t(blockIdx.x) * ANCHOR_HALVES + hw;
+    const bool ok = seg < nseg;
+    const int q = k - ks, nout = m - k;
+    const uint64_t s = ok ? uint64_t(seg) : 0;
+    const int d = __popcll((unsigned long long)s);
+
+    // variable at position c of [front (descending), middle, inner, back (ascending)]
+    int label = -1;
+    if (ok && c < m) {
+        if (c < d) {
+            int cnt = 0;
+            for (int b = nout - 1; b >= 0; --b)
+                if ((s >> b) & 1) {
+                    if (cnt == c) label = k + b;
+                    ++cnt;
+                }
+        } else if (c < d + q) {
+            label = ks + (c - d);
+        } else if (c < d + k) {
+            label = c - d - q;
+        } else {
+            int cnt = 0;
+            for (int b = 0; b < nout; ++b)
+                if (!((s >> b) & 1)) {
+                    if (cnt == c - d - k) label = k + b;
+                    ++cnt;
+                }
+        }
+    }
+    double col[MM];
+#pragma unroll
+    for (int i = 0; i < MM; ++i) col[i] = (label >= 0 && i < m) ? R0[i * m + label] : 0.0;
+
+    double *pc = piv_col[hw];
+    static_for_a<0, MM>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j < m) {
+            wave_lds_sync();  // every lane has read the previous pivot column
+            if (c == j) {
+#pragma unroll
+                for (int i = j; i < MM; ++i) pc[i] = col[i];
+            }
+            wave_lds_sync();  // lane j's column is visible to the whole wave
+            double v[MM];
+            double tailn = 0.0;
+#pragma unroll
+            for (int i = j; i < MM; ++i) v[i] = pc[i];
+#pragma unroll
+            for (int i = j + 1; i < MM; ++i) tailn = fma(v[i], v[i], tailn);
+            const double a = v[j];
+            const double normx2 = fma(a, a, tailn);
+            double alpha = a, f = 0.0, v0 = 0.0;
+            if (normx2 > 0.0) {
+                const double nrm = sqrt(normx2);
+                alpha = a >= 0.0 ? -nrm : nrm;
+                v0 = a - alpha;
+                const double vtv = fma(v0, v0, tailn);
+                double dot = v0 * col[j];
+#pragma unroll
+                for (int i = j + 1; i < MM; ++i) dot = fma(v[i], col[i], dot);
+                f = 2.0 * dot / vtv;
+            }
+            if (c == j) {
+                col[j] = alpha;
+#pragma unroll
+                for (int i = j + 1; i < MM; ++i) col[i] = 0.0;
+            } else {
+                col[j] = fma(-f, v0, col[j]);
+#pragma unroll
+                for (int i = j + 1; i < MM; ++i) col[i] = fma(-f, v[i], col[i]);
+            }
+        }
+    });
+
+    if (!ok || c < d || c >= m) return;
+    const int l = label < k ? label : c - d;  // column slot of this variable
+    TO *an = anchor + seg * int64_t(k) * 32;
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < MM; ++i) {
+        const int r = i - d;
+        if (r >= 0 && r < k) an[r * 32 + l] = TO(col[i]);
+        if (r >= k) t = fma(col[i], col[i], t);
+    }
+    tail[seg * 32 + l] = TO(t);
+}
+
+template <typename TO>
+hipError_t launch_anchors(const double *R0, int m, int k, int ks, int64_t nseg, TO *anchor, TO *tail,
+                          hipStream_t s) {
+    const dim3 grid(unsigned((nseg + ANCHOR_HALVES - 1) / ANCHOR_HALVES)), block(256);
+    const int mm = (m + 3) / 4 * 4;
+    switch (mm) {
+#define GS_ANCHOR_CASE(MMV)                                                                   \
+    case MMV:                                                                                 \
+        hipLaunchKernelGGL((anchor_kernel<MMV, TO>), grid, block, 0, s, R0, m, k, ks, nseg,  \
+                           anchor, tail);                                                     \
+        break;
+        GS_ANCHOR_CASE(4)
+        GS_ANCHOR_CASE(8)
+        GS_ANCHOR_CASE(12)
+        GS_ANCHOR_CASE(16)
+        GS_ANCHOR_CASE(20)
+        GS_ANCHOR_CASE(24)
+        GS_ANCHOR_CASE(28)
+        GS_ANCHOR_CASE(32)
+#undef GS_ANCHOR_CASE
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
+
+template hipError_t launch_anchors<float>(const double *, int, int, int, int64_t, float *, float *,
+                                          hipStream_t);
+template hipError_t launch_anchors<double>(const double *, int, int, int, int64_t, double *,
+                                           double *, hipStream_t);
 
 }  // namespace gs

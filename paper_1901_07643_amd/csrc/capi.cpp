@@ -23,6 +23,10 @@ void free_device(gs_plan_s *p) {
         for (auto e : ev) (void)hipEventDestroy(e);
     p->events.clear();
     (void)hipFree(p->d_prog);
+    (void)hipFree(p->d_lane_seg);
+    (void)hipFree(p->d_lane_loc);
+    p->d_lane_seg = nullptr;
+    p->d_lane_loc = nullptr;
     (void)hipFree(p->d_r0);
     (void)hipFree(p->d_qr_a);
     (void)hipFree(p->d_qr_b);
@@ -30,7 +34,8 @@ void free_device(gs_plan_s *p) {
     (void)hipFree(p->d_tail);
     (void)hipFree(p->d_status);
     p->d_prog = nullptr;
-    p->d_r0 = p->d_qr_a = p->d_qr_b = p->d_anchor = p->d_tail = nullptr;
+    p->d_r0 = p->d_qr_a = p->d_qr_b = nullptr;
+    p->d_anchor = p->d_tail = nullptr;
     p->d_status = nullptr;
     p->done = nullptr;
     p->qr_cap = 0;
@@ -49,7 +54,11 @@ int ensure_workspace(gs_plan_s *p, int64_t n) {
         const size_t r0_b = size_t(p->m) * p->m * sizeof(double);
         const size_t an_b = size_t(p->nseg) * p->k * 32 * sizeof(double);
         const size_t tl_b = size_t(p->nseg) * 32 * sizeof(double);
+        const size_t ls_b = p->lane_seg.size() * sizeof(int32_t);
+        const size_t ll_b = p->lane_loc.size() * sizeof(int8_t);
         if ((e = hipMalloc(&p->d_prog, prog_b)) != hipSuccess ||
+            (e = hipMalloc(&p->d_lane_seg, ls_b)) != hipSuccess ||
+            (e = hipMalloc(&p->d_lane_loc, ll_b)) != hipSuccess ||
             (e = hipMalloc(&p->d_r0, r0_b)) != hipSuccess ||
             (e = hipMalloc(&p->d_anchor, an_b)) != hipSuccess ||
             (e = hipMalloc(&p->d_tail, tl_b)) != hipSuccess ||
@@ -58,6 +67,10 @@ int ensure_workspace(gs_plan_s *p, int64_t n) {
             return fail(GS_ENOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));
         }
         if ((e = hipMemcpy(p->d_prog, p->prog.data(), prog_b, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p->d_lane_seg, p->lane_seg.data(), ls_b, hipMemcpyHostToDevice)) !=
+                hipSuccess ||
+            (e = hipMemcpy(p->d_lane_loc, p->lane_loc.data(), ll_b, hipMemcpyHostToDevice)) !=
+                hipSuccess ||
             (e = hipMemset(p->d_status, 0, sizeof(int) * 4)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming)) != hipSuccess) {
             free_device(p);
@@ -94,7 +107,8 @@ int check_common(gs_plan_s *p, const void *X, int64_t n, int m, int64_t ldx, con
     return GS_OK;
 }
 
-// Enqueue R0 and the anchors; returns GS_OK or an error code.
+// Enqueue R0 and the anchors (stored as T); returns GS_OK or an error code.
+template <typename T>
 int front_half(gs_plan_s *p, const double *X, int64_t n, int m, int64_t ldx, hipStream_t s,
                hipEvent_t *ev) {
     hipError_t e;
@@ -104,8 +118,8 @@ int front_half(gs_plan_s *p, const double *X, int64_t n, int m, int64_t ldx, hip
     if ((e = launch_qr_r0(X, n, m, ldx, p->d_r0, p->d_qr_a, p->d_qr_b, p->d_status, s)) != hipSuccess)
         return hip_fail(e, "R0 QR launch");
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    if ((e = launch_anchors(p->d_r0, p->m, p->k, p->ks, p->nseg, p->d_anchor, p->d_tail, s)) !=
-        hipSuccess)
+    if ((e = launch_anchors<T>(p->d_r0, p->m, p->k, p->ks, p->nseg, static_cast<T *>(p->d_anchor),
+                               static_cast<T *>(p->d_tail), s)) != hipSuccess)
         return hip_fail(e, "anchor launch");
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     return GS_OK;
@@ -130,12 +144,13 @@ int score_all_impl(gs_plan_s *p, const double *X, int64_t n, int m, int64_t ldx,
     if ((st = ensure_workspace(p, n)) != GS_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipEvent_t *ev = new_event_set(p);
-    if ((st = front_half(p, X, n, m, ldx, s, ev)) != GS_OK) return st;
+    if ((st = front_half<T>(p, X, n, m, ldx, s, ev)) != GS_OK) return st;
     hipError_t e;
+    const T *an = static_cast<const T *>(p->d_anchor), *tl = static_cast<const T *>(p->d_tail);
     if constexpr (std::is_same_v<T, float>)
-        e = launch_walk_f32(p, p->d_anchor, p->d_tail, scores, n, what == GS_OUT_BIC, s);
+        e = launch_walk_f32(p, an, tl, scores, n, what == GS_OUT_BIC, s);
     else
-        e = launch_walk_f64(p, p->d_anchor, p->d_tail, scores, n, what == GS_OUT_BIC, s);
+        e = launch_walk_f64(p, an, tl, scores, n, what == GS_OUT_BIC, s);
     if (e != hipSuccess) return hip_fail(e, "walk launch");
     if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");

@@ -19,16 +19,23 @@ struct gs_plan_s {
     int m = 0, k = 0, ks = 0, q = 0;
     int64_t nseg = 0, nsub = 0;
     std::vector<uint32_t> prog;  // 2 words per sub-walk (layout in walk_program.hpp)
+    // segments packed into 64-lane waves: for wave w and lane x, lane_seg[64 w + x] is
+    // the segment code (or -1) and lane_loc[64 w + x] the column slot inside it
+    int64_t nwaves = 0;
+    std::vector<int32_t> lane_seg;
+    std::vector<int8_t> lane_loc;
 
     // device workspace, allocated on first use on `device`
     int device = -1;
     uint32_t *d_prog = nullptr;
+    int32_t *d_lane_seg = nullptr;
+    int8_t *d_lane_loc = nullptr;
     double *d_r0 = nullptr;      // m x m
     double *d_qr_a = nullptr;    // TSQR ping-pong buffers
     double *d_qr_b = nullptr;
     int64_t qr_cap = 0;          // elements per TSQR buffer
-    double *d_anchor = nullptr;  // nseg x k x 32
-    double *d_tail = nullptr;    // nseg x 32
+    void *d_anchor = nullptr;    // nseg x k x 32 (float or double)
+    void *d_tail = nullptr;      // nseg x 32
     int *d_status = nullptr;
     hipStream_t last_stream = nullptr;
     hipEvent_t done = nullptr;
@@ -52,12 +59,17 @@ hipError_t launch_qr_r0(const double *X, int64_t n, int m, int64_t ldx, double *
                         double *bufB, int *status, hipStream_t s);
 int64_t qr_workspace_elems(int64_t n, int m);
 
-// Segment anchors: FP64 R blocks of every segment from R0.
-hipError_t launch_anchors(const double *R0, int m, int k, int ks, int64_t nseg, double *anchor,
-                          double *tail, hipStream_t s);
+// Host planner: pack segments into 64-lane waves (plan.cpp).
+int pack_waves(gs_plan_s *p);
+
+// Segment anchors: R blocks of every segment from R0, computed in FP64 and stored
+// as T (float for the FP32 walk, double for the FP64 walk).
+template <typename T>
+hipError_t launch_anchors(const double *R0, int m, int k, int ks, int64_t nseg, T *anchor, T *tail,
+                          hipStream_t s);
 
 // The walk.  T = float or double; writes the full table.
-hipError_t launch_walk_f32(const gs_plan_s *p, const double *anchor, const double *tail, float *out,
+hipError_t launch_walk_f32(const gs_plan_s *p, const float *anchor, const float *tail, float *out,
                            int64_t n, bool bic, hipStream_t s);
 hipError_t launch_walk_f64(const gs_plan_s *p, const double *anchor, const double *tail,
                            double *out, int64_t n, bool bic, hipStream_t s);

@@ -102,6 +102,59 @@ int build_program(gs_plan_s *p) {
     return GS_OK;
 }
 
+// Pack the segments into 64-lane waves.  Segment s walks k + b(s) columns (b(s)
+// back variables); every segment runs the same program, so a wave costs the same
+// whatever it holds and the aim is few waves.  Best-fit decreasing by width.
+int pack_waves(gs_plan_s *p) {
+    const int k = p->k, nout = p->m - p->k;
+    std::vector<std::vector<int64_t>> by_width(nout + 1);
+    for (int64_t s = 0; s < p->nseg; ++s) {
+        const int b = nout - __builtin_popcountll((unsigned long long)s);
+        by_width[b].push_back(s);
+    }
+    struct Bin {
+        int used = 0;
+        std::vector<int64_t> segs;
+    };
+    std::vector<Bin> bins;
+    std::vector<std::vector<int>> by_free(65);  // bins indexed by free lanes
+    for (int b = nout; b >= 0; --b) {
+        const int w = k + b;
+        if (w > 64) return fail(GS_EINVAL, "planner: segment wider than a wave");
+        for (int64_t s : by_width[b]) {
+            int pick = -1;
+            for (int f = w; f <= 64 && pick < 0; ++f)
+                if (!by_free[f].empty()) {
+                    pick = by_free[f].back();
+                    by_free[f].pop_back();
+                }
+            if (pick < 0) {
+                pick = int(bins.size());
+                bins.emplace_back();
+            }
+            Bin &bn = bins[pick];
+            bn.segs.push_back(s);
+            bn.used += w;
+            by_free[64 - bn.used].push_back(pick);
+        }
+    }
+    p->nwaves = int64_t(bins.size());
+    p->lane_seg.assign(size_t(p->nwaves) * 64, -1);
+    p->lane_loc.assign(size_t(p->nwaves) * 64, 0);
+    for (size_t wv = 0; wv < bins.size(); ++wv) {
+        int off = 0;
+        for (int64_t s : bins[wv].segs) {
+            const int w = k + nout - __builtin_popcountll((unsigned long long)s);
+            for (int l = 0; l < w; ++l) {
+                p->lane_seg[wv * 64 + off + l] = int32_t(s);
+                p->lane_loc[wv * 64 + off + l] = int8_t(l);
+            }
+            off += w;
+        }
+    }
+    return GS_OK;
+}
+
 // ---- host simulation of a plan (for gs_plan_count_emissions) -------------------
 
 template <int KS>
@@ -115,8 +168,33 @@ static int simulate(const gs_plan_s *p, int32_t *counts, int64_t len) {
         const uint64_t high = (S >> (c + 1)) << c;
         return (int64_t(c) << (m - 1)) + int64_t(low | high);
     };
+    // segments in the order the packed waves hold them; each must occupy consecutive
+    // lanes with slots 0..width-1 and appear in exactly one wave
+    std::vector<int64_t> seg_list;
+    std::vector<char> seen(size_t(p->nseg), 0);
+    for (int64_t wv = 0; wv < p->nwaves; ++wv) {
+        int x = 0;
+        while (x < 64) {
+            const int32_t sg = p->lane_seg[size_t(wv * 64 + x)];
+            if (sg < 0) {
+                ++x;
+                continue;
+            }
+            if (sg >= p->nseg || seen[size_t(sg)]) return fail(GS_EINVAL, "simulate: packing");
+            seen[size_t(sg)] = 1;
+            const int w = k + nout - __builtin_popcountll((unsigned long long)sg);
+            if (x + w > 64) return fail(GS_EINVAL, "simulate: segment crosses a wave");
+            for (int l = 0; l < w; ++l)
+                if (p->lane_seg[size_t(wv * 64 + x + l)] != sg ||
+                    p->lane_loc[size_t(wv * 64 + x + l)] != l)
+                    return fail(GS_EINVAL, "simulate: segment lanes");
+            seg_list.push_back(sg);
+            x += w;
+        }
+    }
+    if (int64_t(seg_list.size()) != p->nseg) return fail(GS_EINVAL, "simulate: missing segment");
     std::vector<int> order(k), backs;
-    for (int64_t s = 0; s < p->nseg; ++s) {
+    for (int64_t s : seg_list) {
         uint64_t F = 0;
         backs.clear();
         for (int b = 0; b < nout; ++b) {
@@ -232,10 +310,11 @@ int gs_plan_tuned(int m, int k, int ks, gs_plan_t **out) {
     if (m < 1 || m > GS_MAX_M) return fail(GS_EINVAL, "gs_plan: m must be in 1..30");
     if (ks == 0) ks = m < 5 ? m : 5;
     if (k == 0) {
-        // at least 2^13 segments when m allows (enough half-waves to fill the chip),
-        // and at most 2^13 - 14 Givens steps per segment: the FP32 walk's rounding
-        // error grows with the length of the walk from its FP64 start
-        k = m - 13;
+        // at least 2^15 segments when m allows (after packing, about ten waves per
+        // SIMD, so that the last round of waves is a small part of the run), and at
+        // most 2^13 - 14 Givens steps per segment: the FP32 walk's rounding error
+        // grows with the length of the walk from its FP64 start
+        k = m - 15;
         if (k > kDefaultMaxK) k = kDefaultMaxK;
         if (k < ks) k = ks;
     }
@@ -250,6 +329,7 @@ int gs_plan_tuned(int m, int k, int ks, gs_plan_t **out) {
     p->q = k - ks;
     p->nseg = int64_t(1) << (m - k);
     int st = build_program(p);
+    if (st == GS_OK) st = pack_waves(p);
     if (st != GS_OK) {
         delete p;
         return st;
@@ -270,6 +350,7 @@ int gs_plan_get_info(const gs_plan_t *p, gs_plan_info_t *info) {
     info->sub_per_segment = p->nsub;
     info->swaps_per_segment = (int64_t(1) << p->k) - p->k - 1;
     info->num_families = int64_t(p->m) << (p->m - 1);
+    info->num_waves = p->nwaves;
     return GS_OK;
 }
 

@@ -3,15 +3,18 @@
 // independent segments (Sec. 6), with every visited R turned into RSS and BIC
 // values of the families it solves (Sec. 2) and written to the score table.
 //
-// Mapping to the GPU (one 32-lane half of a wave per segment, two per wave):
-//   - lane l holds the column of one variable (lanes 0..ks-1 the inner block,
-//     ks..k-1 the middle variables, then the back variables).  A column swap is
-//     then only a relabelling; the Givens step mixes two rows in every lane.
+// Mapping to the GPU: segments are packed side by side into 64-lane waves (a
+// segment of k walked and b back variables takes k + b lanes); every segment
+// runs the same program, so a wave costs the same whatever it holds.
+//   - each lane holds the column of one variable of its segment (slots 0..ks-1
+//     the inner block, ks..k-1 the middle variables, then the back variables).
+//     A column swap is then only a relabelling; the Givens step mixes two rows in
+//     every lane.
 //   - the inner block's ks rows live in registers; the inner walk is unrolled at
 //     compile time, so each row index is a constant.  The q middle rows live in
 //     LDS, addressed at run time.
-//   - the pivot column's two entries are broadcast inside the half-wave with
-//     ds_bpermute.
+//   - the pivot column's two entries are broadcast to the segment's lanes with
+//     ds_bpermute (each lane addresses its own segment's pivot slot).
 //   - each inner walk fills one table line (2^ks consecutive entries) per child
 //     column in registers; it is written out with 16-byte stores at its end.
 //
@@ -90,18 +93,26 @@ struct Arith<double> {
     }
 };
 
-// c, s of the step from the pivot's entries (a, b) at rows j, j+1.
-template <typename T>
+// c, s of the step from the pivot's entries (a, b) at rows j, j+1.  With GUARD a
+// zero pair (an exactly rank-deficient prefix) gives c = 1, s = 0; without it the
+// caller knows that R0 has a clearly non-zero diagonal, so a^2 + b^2 > 0.
+template <bool GUARD, typename T>
 __device__ __forceinline__ void givens_cs(T a, T b, T &c, T &s) {
     const T rr = a * a + b * b;
-    const T r = Arith<T>::rsq(rr > Arith<T>::tiny() ? rr : Arith<T>::tiny());
-    c = rr > T(0) ? a * r : T(1);
-    s = b * r;
+    if constexpr (GUARD) {
+        const T r = Arith<T>::rsq(rr > Arith<T>::tiny() ? rr : Arith<T>::tiny());
+        c = rr > T(0) ? a * r : T(1);
+        s = b * r;
+    } else {
+        const T r = Arith<T>::rsq(rr);
+        c = a * r;
+        s = b * r;
+    }
 }
 
 struct WalkArgs {
     int m, k, q;
-    int64_t nseg, nsub;
+    int64_t nseg, nsub, nwaves;
     double row_scale;  // 1/sqrt(n) for BIC (the table then gets RSS/n inside the log), 1 for RSS
     double nlog;       // n ln 2 (FP32 path, log2 in hardware) or n (FP64 path)
     double lnn;        // ln n
@@ -158,12 +169,18 @@ __host__ __device__ constexpr int expand_bit(int i, int c) {
     return ((i >> c) << (c + 1)) | (i & ((1 << c) - 1));
 }
 
-constexpr int WALK_WAVES = 4;  // waves per workgroup (8 segments)
+constexpr int WALK_WAVES = 4;  // waves per workgroup
+#ifndef WALK_MIN_WAVES
+#define WALK_MIN_WAVES 5
+#endif
 
-template <typename T, int KS, bool BIC>
-__global__ __launch_bounds__(64 * WALK_WAVES) void walk_kernel(const double *__restrict__ anchor,
-                                                              const double *__restrict__ tail,
+template <typename T, int KS, bool BIC, int MINW>
+__global__ __launch_bounds__(64 * WALK_WAVES) __attribute__((amdgpu_waves_per_eu(MINW, 8))) void walk_kernel(const T *__restrict__ anchor,
+                                                              const T *__restrict__ tail,
                                                               const uint32_t *__restrict__ prog,
+                                                              const int32_t *__restrict__ lane_seg,
+                                                              const int8_t *__restrict__ lane_loc,
+                                                              const int *__restrict__ status,
                                                               T *__restrict__ out, WalkArgs a) {
     constexpr int N = InnerProgram<KS>::N;
     constexpr int NS = 1 << KS;
@@ -171,16 +188,21 @@ __global__ __launch_bounds__(64 * WALK_WAVES) void walk_kernel(const double *__r
 
     const int wave = threadIdx.x >> 6;
     const int lane64 = threadIdx.x & 63;
-    const int half = lane64 >> 5;
-    const int lane = lane64 & 31;
-    const int64_t seg = (int64_t(blockIdx.x) * WALK_WAVES + wave) * 2 + half;
-    const bool seg_ok = seg < a.nseg;
+    const int64_t wid = int64_t(blockIdx.x) * WALK_WAVES + wave;
+    // this lane's segment and its column slot l inside it
+    const int32_t segv = wid < a.nwaves ? lane_seg[wid * 64 + lane64] : -1;
+    const bool seg_ok = segv >= 0;
+    const int lane = seg_ok ? int(lane_loc[wid * 64 + lane64]) : 63;
     const int m = a.m, k = a.k, q = a.q, nout = m - k;
-    const int bbase = half * 128;  // ds_bpermute byte address of lane 0 of this half
+    const int bbase = (lane64 - (seg_ok ? lane : 0)) * 4;  // ds_bpermute address of slot 0
     T(*L)[64] = Lrows[wave];
+    // lanes holding inner slot c of their segment (the pivots of the inner walk)
+    uint64_t slot_mask[KS];
+#pragma unroll
+    for (int c = 0; c < KS; ++c) slot_mask[c] = __builtin_amdgcn_ballot_w64(seg_ok && lane == c);
 
-    // lane -> variable label and class: 1 inner, 2 middle, 3 back, 0 unused
-    const uint64_t scode = seg_ok ? uint64_t(seg) : 0;
+    // slot -> variable label and class: 1 inner, 2 middle, 3 back, 0 unused
+    const uint64_t scode = seg_ok ? uint64_t(segv) : 0;
     int label = -1, cls = 0;
     if (lane < KS) {
         label = lane;
@@ -203,34 +225,34 @@ __global__ __launch_bounds__(64 * WALK_WAVES) void walk_kernel(const double *__r
     const uint64_t Fbits = scode << k;
     const int nF = __popcll((unsigned long long)scode);
 
-    // anchor (FP64) -> working precision
-    const double rs = a.row_scale;
-    const int64_t sidx = seg_ok ? seg : 0;
-    const double *an = anchor + sidx * int64_t(k) * 32;
+    // anchor -> working precision (BIC: rows scaled by 1/sqrt(n))
+    const T rs = T(a.row_scale);
+    const T *an = anchor + int64_t(seg_ok ? segv : 0) * k * 32 + (seg_ok ? lane : 0);
     T I[KS];
 #pragma unroll
-    for (int i = 0; i < KS; ++i) I[i] = seg_ok ? T(an[(q + i) * 32 + lane] * rs) : T(0);
-    for (int p = 0; p < q; ++p) L[p][lane64] = seg_ok ? T(an[p * 32 + lane] * rs) : T(0);
-    const T tl = seg_ok ? T(tail[sidx * 32 + lane] * rs * rs) : T(0);
+    for (int i = 0; i < KS; ++i) I[i] = seg_ok ? an[(q + i) * 32] * rs : T(0);
+    for (int p = 0; p < q; ++p) L[p][lane64] = seg_ok ? an[p * 32] * rs : T(0);
+    const T tl = seg_ok ? tail[int64_t(segv) * 32 + lane] * rs * rs : T(0);
     const T nlog = T(a.nlog), lnn = T(a.lnn);
 
     int z = q;
-    for (int64_t t = 0; t < a.nsub; ++t) {
-        const uint32_t w0 = prog[2 * t], w1 = prog[2 * t + 1];
-        const bool fwd = (t & 1) == 0;
+    // One sub-walk: the transition into it, the inner walk, the table writes.  FWD is
+    // the direction of the inner walk (forward on even t), which fixes the inner
+    // block's ordering at compile time.
+    auto sub_walk = [&](auto gc, auto dirc, uint32_t w0, uint32_t w1) {
+        constexpr bool G = decltype(gc)::value;
+        constexpr bool FWD = decltype(dirc)::value;
+        constexpr auto &ord = FWD ? kInner<KS>.order_f : kInner<KS>.order_r;
         if (w1 & SubWord::kHasTransition) {
             if (w1 & SubWord::kHasMid) {
                 // swap of two middle variables on the same side of the inner block
                 const int j = int((w1 >> 2) & 31), piv = int((w1 >> 8) & 31);
                 const int addr = bbase + piv * 4;
-                T x = L[j][lane64], y = L[j + 1][lane64];
+                const T x = L[j][lane64], y = L[j + 1][lane64];
                 T c, s;
-                givens_cs(bcast(x, addr), bcast(y, addr), c, s);
-                const T nx = c * x + s * y;
-                T ny = s * x - c * y;
-                if (lane == piv) ny = T(0);
-                L[j][lane64] = nx;
-                L[j + 1][lane64] = ny;
+                givens_cs<G>(bcast(x, addr), bcast(y, addr), c, s);
+                L[j][lane64] = c * x + s * y;
+                L[j + 1][lane64] = lane == piv ? T(0) : s * x - c * y;
             }
             const int v = int((w1 >> 16) & 31);
             if (w1 & SubWord::kCrossLeft) {
@@ -240,11 +262,10 @@ __global__ __launch_bounds__(64 * WALK_WAVES) void walk_kernel(const double *__r
                 static_for<0, KS>([&](auto ic) {
                     constexpr int i = KS - 1 - decltype(ic)::value;
                     T c, s;
-                    givens_cs(bcast(I[i], addr), bcast(carry, addr), c, s);
+                    givens_cs<G>(bcast(I[i], addr), bcast(carry, addr), c, s);
                     const T top = c * I[i] + s * carry;
-                    T bot = s * I[i] - c * carry;
-                    if (lane == v) bot = T(0);
-                    I[i] = bot;
+                    const T bot = s * I[i] - c * carry;
+                    I[i] = lane == v ? T(0) : bot;
                     carry = top;
                 });
                 L[z][lane64] = carry;
@@ -254,15 +275,13 @@ __global__ __launch_bounds__(64 * WALK_WAVES) void walk_kernel(const double *__r
                 T carry = L[z - 1][lane64];
                 static_for<0, KS>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
-                    const int piv = fwd ? kInner<KS>.order_f[i] : kInner<KS>.order_r[i];
+                    constexpr int piv = ord[i];
                     const int addr = bbase + piv * 4;
                     T c, s;
-                    givens_cs(bcast(carry, addr), bcast(I[i], addr), c, s);
+                    givens_cs<G>(bcast(carry, addr), bcast(I[i], addr), c, s);
                     const T top = c * carry + s * I[i];
-                    T bot = s * carry - c * I[i];
-                    if (lane == piv) bot = T(0);
+                    carry = select_lanes(slot_mask[piv], T(0), s * carry - c * I[i]);
                     I[i] = top;
-                    carry = bot;
                 });
                 L[z - 1][lane64] = carry;
                 --z;
@@ -290,32 +309,26 @@ __global__ __launch_bounds__(64 * WALK_WAVES) void walk_kernel(const double *__r
             if constexpr (BIC) return Arith<T>::score(rss, nlog, cst[u]);
             else return rss;
         };
-        auto inner_walk = [&](auto dirc) {
-            constexpr bool FWD = decltype(dirc)::value;
-            static_for<0, KS + 1>([&](auto pc) {
-                constexpr int pl = decltype(pc)::value;
-                constexpr int U = FWD ? kInner<KS>.init_f[pl] : kInner<KS>.init_r[pl];
-                o[U] = score(sfx[pl], popcount_c(U));
-            });
-            static_for<0, N>([&](auto sc) {
-                constexpr int st = decltype(sc)::value;
-                constexpr int J = FWD ? kInner<KS>.j_f[st] : kInner<KS>.j_r[st];
-                constexpr int PV = FWD ? kInner<KS>.piv_f[st] : kInner<KS>.piv_r[st];
-                constexpr int U = FWD ? kInner<KS>.mask_f[st] : kInner<KS>.mask_r[st];
-                const int addr = bbase + PV * 4;
-                T c, s;
-                givens_cs(bcast(I[J], addr), bcast(I[J + 1], addr), c, s);
-                const T x = I[J], y = I[J + 1];
-                I[J] = c * x + s * y;
-                T ny = s * x - c * y;
-                if (lane == PV) ny = T(0);
-                I[J + 1] = ny;
-                sfx[J + 1] = ny * ny + sfx[J + 2];
-                o[U] = score(sfx[J + 1], popcount_c(U));
-            });
-        };
-        if (fwd) inner_walk(std::true_type{});
-        else inner_walk(std::false_type{});
+        static_for<0, KS + 1>([&](auto pc) {
+            constexpr int pl = decltype(pc)::value;
+            constexpr int U = FWD ? kInner<KS>.init_f[pl] : kInner<KS>.init_r[pl];
+            o[U] = score(sfx[pl], popcount_c(U));
+        });
+        static_for<0, N>([&](auto sc) {
+            constexpr int st = decltype(sc)::value;
+            constexpr int J = FWD ? kInner<KS>.j_f[st] : kInner<KS>.j_r[st];
+            constexpr int PV = FWD ? kInner<KS>.piv_f[st] : kInner<KS>.piv_r[st];
+            constexpr int U = FWD ? kInner<KS>.mask_f[st] : kInner<KS>.mask_r[st];
+            const int addr = bbase + PV * 4;
+            T c, s;
+            givens_cs<G>(bcast(I[J], addr), bcast(I[J + 1], addr), c, s);
+            const T x = I[J], y = I[J + 1];
+            I[J] = c * x + s * y;
+            const T ny = select_lanes(slot_mask[PV], T(0), s * x - c * y);
+            I[J + 1] = ny;
+            sfx[J + 1] = ny * ny + sfx[J + 2];
+            o[U] = score(sfx[J + 1], popcount_c(U));
+        });
 
         // write this sub-walk's table lines
         const uint64_t Shi = Fbits | (uint64_t(omask) << KS);
@@ -328,8 +341,7 @@ __global__ __launch_bounds__(64 * WALK_WAVES) void walk_kernel(const double *__r
                 T val = o[expand_bit(i, 0)];
                 static_for<1, KS>([&](auto cc) {
                     constexpr int c = decltype(cc)::value;
-                    constexpr uint64_t lanes = (uint64_t(1) << c) | (uint64_t(1) << (32 + c));
-                    val = select_lanes(lanes, o[expand_bit(i, c)], val);
+                    val = select_lanes(slot_mask[c], o[expand_bit(i, c)], val);
                 });
                 h[i] = val;
             });
@@ -339,30 +351,47 @@ __global__ __launch_bounds__(64 * WALK_WAVES) void walk_kernel(const double *__r
             const uint64_t high = (Shi >> (label + 1)) << label;
             store_line<NS>(out + cbase + int64_t(low | high), o);
         }
-    }
+    };
+    auto run = [&](auto gc) {
+        for (int64_t t = 0; t < a.nsub; ++t) {
+            const uint32_t w0 = prog[2 * t], w1 = prog[2 * t + 1];
+            if ((t & 1) == 0) sub_walk(gc, std::true_type{}, w0, w1);
+            else sub_walk(gc, std::false_type{}, w0, w1);
+        }
+    };
+    // The R0 kernel has flagged a (near) rank-deficient X: only then can a Givens
+    // pivot pair be exactly zero.  The FP64 walk always takes the guarded path.
+    if (std::is_same_v<T, double> || (status[0] & GS_FLAG_RANK)) run(std::true_type{});
+    else run(std::false_type{});
 }
 
+// Register budget: the FP32 kernels with inner blocks up to 5 are held to 96 VGPRs
+// (5 waves per SIMD); the others take what they need.
+template <typename T, int KS>
+constexpr int kMinWaves = (std::is_same_v<T, float> && KS <= 5) ? WALK_MIN_WAVES : 1;
+
 template <typename T, bool BIC>
-static hipError_t launch_walk_t(const gs_plan_s *p, const double *anchor, const double *tail,
-                                T *out, int64_t n, hipStream_t s) {
+static hipError_t launch_walk_t(const gs_plan_s *p, const T *anchor, const T *tail, T *out,
+                                int64_t n, hipStream_t s) {
     WalkArgs a;
     a.m = p->m;
     a.k = p->k;
     a.q = p->q;
     a.nseg = p->nseg;
     a.nsub = p->nsub;
+    a.nwaves = p->nwaves;
     const double dn = double(n);
     a.row_scale = BIC ? 1.0 / std::sqrt(dn) : 1.0;
     a.nlog = std::is_same_v<T, float> ? dn * 0.6931471805599453 : dn;
     a.lnn = std::log(dn);
-    const int64_t segs_per_block = 2 * WALK_WAVES;
-    const dim3 grid(unsigned((p->nseg + segs_per_block - 1) / segs_per_block));
+    const dim3 grid(unsigned((p->nwaves + WALK_WAVES - 1) / WALK_WAVES));
     const dim3 block(64 * WALK_WAVES);
     switch (p->ks) {
 #define GS_WALK_CASE(KSV)                                                                   \
     case KSV:                                                                               \
-        hipLaunchKernelGGL((walk_kernel<T, KSV, BIC>), grid, block, 0, s, anchor, tail,    \
-                           p->d_prog, out, a);                                              \
+        hipLaunchKernelGGL((walk_kernel<T, KSV, BIC, kMinWaves<T, KSV>>), grid, block, 0, s, \
+                           anchor, tail,                                                    \
+                           p->d_prog, p->d_lane_seg, p->d_lane_loc, p->d_status, out, a);   \
         break;
         GS_WALK_CASE(1)
         GS_WALK_CASE(2)
@@ -376,7 +405,7 @@ static hipError_t launch_walk_t(const gs_plan_s *p, const double *anchor, const 
     return hipGetLastError();
 }
 
-hipError_t launch_walk_f32(const gs_plan_s *p, const double *anchor, const double *tail, float *out,
+hipError_t launch_walk_f32(const gs_plan_s *p, const float *anchor, const float *tail, float *out,
                            int64_t n, bool bic, hipStream_t s) {
     return bic ? launch_walk_t<float, true>(p, anchor, tail, out, n, s)
                : launch_walk_t<float, false>(p, anchor, tail, out, n, s);
