@@ -46,6 +46,8 @@ def _lib():
         lib.or_score_indices.argtypes = [vp, i64, ctypes.c_int, i64, vp, i64, vp, ctypes.c_int,
                                          ctypes.c_int]
         lib.or_score_indices.restype = ctypes.c_int
+        lib.or_grad_from_gbar.argtypes = [vp, i64, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int]
+        lib.or_grad_from_gbar.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -108,3 +110,45 @@ def score_indices(X, idx, what: int = OUT_BIC, threads: int | None = None) -> np
     if st != 0:
         raise RuntimeError(f"oracle score_indices failed ({st})")
     return out
+
+
+def grad_from_gbar(X, gbar, threads: int | None = None):
+    """dL/dX = 2 X A with A = sum gbar(c,S) w w^T (gbar = dL/dRSS in table order).
+    Returns (dX (n, m), A (m, m))."""
+    X = _as_X(X)
+    n, m = X.shape
+    gbar = np.ascontiguousarray(np.asarray(gbar, dtype=np.float64))
+    if gbar.shape != (num_families(m),):
+        raise ValueError("gbar must hold one value per family")
+    A = np.empty((m, m), dtype=np.float64)
+    dX = np.empty((n, m), dtype=np.float64)
+    st = _lib().or_grad_from_gbar(X.ctypes.data, n, m, m, gbar.ctypes.data, A.ctypes.data,
+                                 dX.ctypes.data, threads or default_threads())
+    if st != 0:
+        raise RuntimeError(f"oracle gradient failed ({st})")
+    return dX, A
+
+
+def logsumexp_loss(bic: np.ndarray, m: int):
+    """L = sum over children of logsumexp over parent sets of -BIC, and dL/dBIC."""
+    t = np.asarray(bic, dtype=np.float64).reshape(m, -1)
+    z = -t
+    zmax = z.max(axis=1, keepdims=True)
+    e = np.exp(z - zmax)
+    ssum = e.sum(axis=1, keepdims=True)
+    L = float((zmax[:, 0] + np.log(ssum[:, 0])).sum())
+    dbic = -(e / ssum)
+    return L, dbic.reshape(-1)
+
+
+def loss_and_grad(X, threads: int | None = None):
+    """The differentiation workload's loss on the oracle's BIC table and its gradient
+    dL/dX by the closed form.  Returns (L, dX, dL/dBIC, RSS table)."""
+    X = _as_X(X)
+    n, m = X.shape
+    rss_t = score_all(X, OUT_RSS, threads)
+    bic_t = score_all(X, OUT_BIC, threads)
+    L, dbic = logsumexp_loss(bic_t, m)
+    gbar = dbic * (n / rss_t)
+    dX, _ = grad_from_gbar(X, gbar, threads)
+    return L, dX, dbic, rss_t

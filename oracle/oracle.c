@@ -189,3 +189,144 @@ int or_score_indices(const double *X, int64_t n, int m, int64_t ldx, const int64
     if (!idx && count > 0) return -1;
     return run_parallel(X, n, m, ldx, idx, count, out, what, nthreads);
 }
+
+/* ---------------------------------------------------------------------------------
+ * Gradient oracle.  For RSS(c,S) = min_beta ||x_c - X_S beta||^2 the envelope theorem
+ * gives d RSS / d X = 2 r w^T with r = X w the residual and w = e_c - beta (beta placed
+ * at the rows of S).  For any loss L of the table with gbar(c,S) = dL/dRSS(c,S):
+ *     dL/dX = 2 X A,   A = sum_{c,S} gbar(c,S) w w^T   (m x m).
+ * beta comes from the same Householder QR as the RSS (back-substitution on R_SS).
+ * ------------------------------------------------------------------------------- */
+
+/* beta of x_child on the columns in mask: QR of [X_S | x_c], then R_SS beta = (Q^T x_c)_S. */
+static void beta_householder(const double *X, int64_t n, int m, int64_t ldx, int child,
+                             uint64_t mask, double *work, double *beta_full) {
+    int cols[64];
+    int s = 0;
+    for (int v = 0; v < m; ++v)
+        if ((mask >> v) & 1ull) cols[s++] = v;
+    cols[s] = child;
+    const int w = s + 1;
+    for (int j = 0; j < w; ++j) {
+        double *dst = work + (int64_t)j * n;
+        const double *src = X + cols[j];
+        for (int64_t i = 0; i < n; ++i) dst[i] = src[i * ldx];
+    }
+    for (int j = 0; j < s; ++j) {
+        double *a = work + (int64_t)j * n;
+        double normx2 = 0.0;
+        for (int64_t i = j; i < n; ++i) normx2 += a[i] * a[i];
+        if (normx2 == 0.0) continue;
+        double normx = sqrt(normx2);
+        double alpha = a[j] >= 0.0 ? -normx : normx;
+        double v0 = a[j] - alpha;
+        double vtv = normx2 - a[j] * a[j] + v0 * v0;
+        for (int c = j + 1; c < w; ++c) {
+            double *b = work + (int64_t)c * n;
+            double dot = v0 * b[j];
+            for (int64_t i = j + 1; i < n; ++i) dot += a[i] * b[i];
+            double f = 2.0 * dot / vtv;
+            b[j] -= f * v0;
+            for (int64_t i = j + 1; i < n; ++i) b[i] -= f * a[i];
+        }
+        a[j] = alpha;
+        for (int64_t i = j + 1; i < n; ++i) a[i] = 0.0;
+    }
+    /* back-substitution: R_SS beta = y_S, R_SS[i][j] = work[j*n + i] */
+    const double *y = work + (int64_t)s * n;
+    double bl[64];
+    for (int i = s - 1; i >= 0; --i) {
+        double acc = y[i];
+        for (int j = i + 1; j < s; ++j) acc -= work[(int64_t)j * n + i] * bl[j];
+        bl[i] = acc / work[(int64_t)i * n + i];
+    }
+    for (int v = 0; v < m; ++v) beta_full[v] = 0.0;
+    for (int i = 0; i < s; ++i) beta_full[cols[i]] = bl[i];
+}
+
+typedef struct {
+    const double *X;
+    int64_t n;
+    int m;
+    int64_t ldx;
+    const double *gbar;
+    int64_t begin, end;
+    double A[64 * 64];
+    int status;
+} gjob_t;
+
+static void *run_gjob(void *p) {
+    gjob_t *jb = (gjob_t *)p;
+    const int m = jb->m;
+    double *work = (double *)malloc(sizeof(double) * (size_t)jb->n * (size_t)(m + 1));
+    if (!work) {
+        jb->status = -3;
+        return NULL;
+    }
+    double w[64];
+    for (int i = 0; i < m * m; ++i) jb->A[i] = 0.0;
+    for (int64_t t = jb->begin; t < jb->end; ++t) {
+        const double g = jb->gbar[t];
+        if (g == 0.0) continue;
+        int c;
+        uint64_t mask;
+        or_family_decode(m, t, &c, &mask);
+        beta_householder(jb->X, jb->n, m, jb->ldx, c, mask, work, w);
+        for (int v = 0; v < m; ++v) w[v] = -w[v];
+        w[c] = 1.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) jb->A[i * m + j] += g * w[i] * w[j];
+    }
+    free(work);
+    return NULL;
+}
+
+/* A = sum_{c,S} gbar(c,S) w w^T over the whole table (gbar in table order), then
+ * dX = 2 X A (n x m, row stride m).  Threads reduce their partial A in a fixed order. */
+int or_grad_from_gbar(const double *X, int64_t n, int m, int64_t ldx, const double *gbar,
+                      double *A_out, double *dX, int nthreads) {
+    if (!X || !gbar || n < 1 || m < 1 || m > 40 || ldx < m) return -1;
+    const int64_t N = or_num_families(m);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 64) nthreads = 64;
+    gjob_t *jobs = (gjob_t *)calloc((size_t)nthreads, sizeof(gjob_t));
+    pthread_t th[64];
+    if (!jobs) return -3;
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t].X = X;
+        jobs[t].n = n;
+        jobs[t].m = m;
+        jobs[t].ldx = ldx;
+        jobs[t].gbar = gbar;
+        jobs[t].begin = N * t / nthreads;
+        jobs[t].end = N * (t + 1) / nthreads;
+        if (nthreads > 1) {
+            if (pthread_create(&th[t], NULL, run_gjob, &jobs[t]) != 0) {
+                run_gjob(&jobs[t]);
+                th[t] = 0;
+            }
+        } else {
+            run_gjob(&jobs[t]);
+        }
+    }
+    double A[64 * 64];
+    for (int i = 0; i < m * m; ++i) A[i] = 0.0;
+    int st = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        if (nthreads > 1 && th[t]) pthread_join(th[t], NULL);
+        if (jobs[t].status) st = jobs[t].status;
+        for (int i = 0; i < m * m; ++i) A[i] += jobs[t].A[i];
+    }
+    free(jobs);
+    if (A_out)
+        for (int i = 0; i < m * m; ++i) A_out[i] = A[i];
+    if (dX) {
+        for (int64_t r = 0; r < n; ++r)
+            for (int j = 0; j < m; ++j) {
+                double acc = 0.0;
+                for (int i = 0; i < m; ++i) acc += X[r * ldx + i] * A[i * m + j];
+                dX[r * m + j] = 2.0 * acc;
+            }
+    }
+    return st;
+}
