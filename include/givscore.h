@@ -129,6 +129,25 @@ int gs_score_all(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx
 int gs_score_all_f64(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
                      double *scores, int what, void *stream);
 
+/* Reverse mode of gs_score_all: given dscores = d(loss)/d(score) for every family
+ * (table order; the score is BIC or RSS as selected by `what`), writes
+ * dX = d(loss)/dX.  Not in the paper: the adjoint of its method.
+ *   X: device, the same n x m FP64 data as for gs_score_all (row stride ldx).
+ *   dscores: device, m * 2^(m-1) floats.
+ *   dX: device, n x m FP64, row stride lddx >= m; overwritten.
+ * The FP32 walk is replayed and then undone step by step in FP32: every Givens step
+ * is recovered from the rotated matrix, nothing is stored per step.  The reverse
+ * rules of the segment-anchor QRs and of R0 are applied in FP64; all sums run in a
+ * fixed order, so the result is reproducible bit for bit.  Workspace: about
+ * 2^(m-k) (k + m^2/32 + 1) x 256 bytes, allocated on the first call. */
+int gs_score_backward(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
+                      const float *dscores, int what, double *dX, int64_t lddx, void *stream);
+
+/* Same with the walk replayed and undone in FP64 and FP64 dscores. */
+int gs_score_backward_f64(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
+                          const double *dscores, int what, double *dX, int64_t lddx,
+                          void *stream);
+
 /* Wait for the plan's last enqueued work and return GS_OK, GS_ERANK or
  * GS_ENOTFINITE from the device status word of that call (GS_EHIP on a runtime
  * failure). */

@@ -23,7 +23,7 @@ from ._abi import (GS_EINVAL, GS_ENOTFINITE, GS_ERANK, GS_MAX_M, GS_OK, GS_OUT_B
                    GivScoreError, PlanInfo, check, last_error, lib)
 
 __all__ = [
-    "Plan", "score_all", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
+    "Plan", "score_all", "score_backward", "givscore", "GivScore", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
     "GS_OK", "GS_EINVAL", "GS_ERANK", "GS_ENOTFINITE", "GS_MAX_M", "lib", "last_error",
 ]
 
@@ -160,3 +160,76 @@ def score_all(X, plan: Plan | None = None, what: str = "bic", precision: str = "
         if check_status:
             check(plan.status())
     return out
+
+
+def score_backward(X, dscores, plan: Plan | None = None, what: str = "bic",
+                   precision: str = "fp32", out=None, check_status: bool = True):
+    """d(loss)/dX (n, m) float64 from dscores = d(loss)/d(score) for every family.
+
+    precision "fp32" replays and undoes the FP32 walk (dscores float32); "fp64" the FP64
+    walk (dscores float64).  The anchor and R0 QR adjoints run in FP64."""
+    import torch
+    n, m, ldx = _check_X(X, plan.m if plan else None)
+    plan = plan or Plan(m)
+    w = {"bic": GS_OUT_BIC, "rss": GS_OUT_RSS}[what]
+    dtype = {"fp32": torch.float32, "fp64": torch.float64}[precision]
+    N = num_families(m)
+    if (not isinstance(dscores, torch.Tensor) or dscores.dtype != dtype
+            or dscores.numel() != N or dscores.device != X.device):
+        raise ValueError(f"dscores must be a {dtype} device tensor of m*2^(m-1) elements")
+    dscores = dscores.contiguous()
+    if out is None:
+        out = torch.empty((n, m), dtype=torch.float64, device=X.device)
+    elif out.shape != (n, m) or out.dtype != torch.float64 or out.stride(1) != 1:
+        raise ValueError("out must be an (n, m) float64 tensor with unit column stride")
+    fn = lib().gs_score_backward if precision == "fp32" else lib().gs_score_backward_f64
+    with torch.cuda.device(X.device):
+        check(fn(plan.handle, ctypes.c_void_p(X.data_ptr()), n, m, ldx,
+                 ctypes.c_void_p(dscores.data_ptr()), w, ctypes.c_void_p(out.data_ptr()),
+                 out.stride(0), _stream(X.device)))
+        if check_status:
+            check(plan.status())
+    return out
+
+
+def _make_function():
+    import torch
+
+    class GivScore(torch.autograd.Function):
+        """scores = score_all(X) with a hand-written backward (gs_score_backward)."""
+
+        @staticmethod
+        def forward(ctx, X, plan, what, precision):
+            scores = score_all(X, plan=plan, what=what, precision=precision)
+            ctx.save_for_backward(X)
+            ctx.plan, ctx.what, ctx.precision = plan, what, precision
+            return scores
+
+        @staticmethod
+        def backward(ctx, dscores):
+            (X,) = ctx.saved_tensors
+            dtype = torch.float32 if ctx.precision == "fp32" else torch.float64
+            dX = score_backward(X, dscores.to(dtype).contiguous(), plan=ctx.plan, what=ctx.what,
+                                precision=ctx.precision)
+            return dX, None, None, None
+
+    return GivScore
+
+
+_GIVSCORE_FN = None
+
+
+def __getattr__(name):
+    global _GIVSCORE_FN
+    if name == "GivScore":
+        if _GIVSCORE_FN is None:
+            _GIVSCORE_FN = _make_function()
+        return _GIVSCORE_FN
+    raise AttributeError(name)
+
+
+def givscore(X, plan: Plan | None = None, what: str = "bic", precision: str = "fp32"):
+    """Differentiable scores of every family of X (torch.autograd)."""
+    n, m, _ = _check_X(X, plan.m if plan else None)
+    plan = plan or Plan(m)
+    return __getattr__("GivScore").apply(X, plan, what, precision)

@@ -65,6 +65,8 @@ def lib():
         "gs_qr_r0": (i32, [vp, vp, i64, i32, i64, vp, vp]),
         "gs_score_all": (i32, [vp, vp, i64, i32, i64, vp, i32, vp]),
         "gs_score_all_f64": (i32, [vp, vp, i64, i32, i64, vp, i32, vp]),
+        "gs_score_backward": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
+        "gs_score_backward_f64": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
         "gs_sync_status": (i32, [vp]),
         "gs_set_timing": (i32, [vp, i32]),
         "gs_get_timing": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),

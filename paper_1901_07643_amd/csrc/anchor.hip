@@ -9,8 +9,10 @@
 // squared sums (the "tail" of each back column).
 //
 // One 32-lane half-wave per segment; lane c holds column c of R0 P in registers
-// (rows 0..MM-1, MM >= m, zero below m).  Each Householder step broadcasts the
-// pivot column through LDS and updates every column at once.
+// (rows 0..MM-1, MM >= m).  Each Householder step broadcasts the pivot column
+// through LDS and updates every column at once; the rows are then signed so that
+// the diagonal is non-negative (the walk keeps it so, which lets its adjoint
+// recover every rotation from the rotated matrix).
 //
 // Output layout, per segment s, by column slot l (l < k: variable l; l = k + i:
 // the i-th back variable in ascending label order):
@@ -23,27 +25,11 @@
 #include <type_traits>
 
 #include "gs_internal.hpp"
+#include "segment_qr.hpp"
 
 namespace gs {
 
-template <int I, int N, typename Fn>
-__device__ __forceinline__ void static_for_a(Fn &&f) {
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        static_for_a<I + 1, N>(f);
-    }
-}
-
 constexpr int ANCHOR_HALVES = 8;  // segments per 256-thread workgroup
-
-// Order LDS accesses of one wave: lane j writes the pivot column, the others read
-// it.  Without this the compiler may treat the cross-lane exchange as a data race
-// and move the reads ahead of the write.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <int MM, typename TO>
 __global__ __launch_bounds__(256) void anchor_kernel(const double *__restrict__ R0, int m, int k,
@@ -54,77 +40,11 @@ __global__ __launch_bounds__(256) void anchor_kernel(const double *__restrict__ 
     const int c = threadIdx.x & 31;
     const int64_t seg = int64_t(blockIdx.x) * ANCHOR_HALVES + hw;
     const bool ok = seg < nseg;
-    const int q = k - ks, nout = m - k;
     const uint64_t s = ok ? uint64_t(seg) : 0;
     const int d = __popcll((unsigned long long)s);
-
-    // variable at position c of [front (descending), middle, inner, back (ascending)]
-    int label = -1;
-    if (ok && c < m) {
-        if (c < d) {
-            int cnt = 0;
-            for (int b = nout - 1; b >= 0; --b)
-                if ((s >> b) & 1) {
-                    if (cnt == c) label = k + b;
-                    ++cnt;
-                }
-        } else if (c < d + q) {
-            label = ks + (c - d);
-        } else if (c < d + k) {
-            label = c - d - q;
-        } else {
-            int cnt = 0;
-            for (int b = 0; b < nout; ++b)
-                if (!((s >> b) & 1)) {
-                    if (cnt == c - d - k) label = k + b;
-                    ++cnt;
-                }
-        }
-    }
+    const int label = ok ? segment_label(s, c, m, k, ks) : -1;
     double col[MM];
-#pragma unroll
-    for (int i = 0; i < MM; ++i) col[i] = (label >= 0 && i < m) ? R0[i * m + label] : 0.0;
-
-    double *pc = piv_col[hw];
-    static_for_a<0, MM>([&](auto jc) {
-        constexpr int j = decltype(jc)::value;
-        if (j < m) {
-            wave_lds_sync();  // every lane has read the previous pivot column
-            if (c == j) {
-#pragma unroll
-                for (int i = j; i < MM; ++i) pc[i] = col[i];
-            }
-            wave_lds_sync();  // lane j's column is visible to the whole wave
-            double v[MM];
-            double tailn = 0.0;
-#pragma unroll
-            for (int i = j; i < MM; ++i) v[i] = pc[i];
-#pragma unroll
-            for (int i = j + 1; i < MM; ++i) tailn = fma(v[i], v[i], tailn);
-            const double a = v[j];
-            const double normx2 = fma(a, a, tailn);
-            double alpha = a, f = 0.0, v0 = 0.0;
-            if (normx2 > 0.0) {
-                const double nrm = sqrt(normx2);
-                alpha = a >= 0.0 ? -nrm : nrm;
-                v0 = a - alpha;
-                const double vtv = fma(v0, v0, tailn);
-                double dot = v0 * col[j];
-#pragma unroll
-                for (int i = j + 1; i < MM; ++i) dot = fma(v[i], col[i], dot);
-                f = 2.0 * dot / vtv;
-            }
-            if (c == j) {
-                col[j] = alpha;
-#pragma unroll
-                for (int i = j + 1; i < MM; ++i) col[i] = 0.0;
-            } else {
-                col[j] = fma(-f, v0, col[j]);
-#pragma unroll
-                for (int i = j + 1; i < MM; ++i) col[i] = fma(-f, v[i], col[i]);
-            }
-        }
-    });
+    segment_qr<MM>(R0, m, label, c, col, piv_col[hw]);
 
     if (!ok || c < d || c >= m) return;
     const int l = label < k ? label : c - d;  // column slot of this variable

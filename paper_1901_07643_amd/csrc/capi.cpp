@@ -33,6 +33,13 @@ void free_device(gs_plan_s *p) {
     (void)hipFree(p->d_anchor);
     (void)hipFree(p->d_tail);
     (void)hipFree(p->d_status);
+    (void)hipFree(p->d_anchorbar);
+    (void)hipFree(p->d_tailbar);
+    (void)hipFree(p->d_vout);
+    (void)hipFree(p->d_partial);
+    (void)hipFree(p->d_B);
+    (void)hipFree(p->d_K);
+    p->d_anchorbar = p->d_tailbar = p->d_vout = p->d_partial = p->d_B = p->d_K = nullptr;
     p->d_prog = nullptr;
     p->d_r0 = p->d_qr_a = p->d_qr_b = nullptr;
     p->d_anchor = p->d_tail = nullptr;
@@ -158,9 +165,71 @@ int score_all_impl(gs_plan_s *p, const double *X, int64_t n, int m, int64_t ldx,
     return GS_OK;
 }
 
+int ensure_adjoint_workspace(gs_plan_s *p) {
+    if (p->d_anchorbar) return GS_OK;
+    const size_t m2 = size_t(p->m) * p->m;
+    const size_t nch = size_t(adjoint_partial_chunks(p->nseg));
+    hipError_t e;
+    if ((e = hipMalloc(&p->d_anchorbar, size_t(p->nseg) * p->k * 32 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&p->d_tailbar, size_t(p->nseg) * 32 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&p->d_vout, size_t(p->nseg) * m2 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&p->d_partial, nch * m2 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&p->d_B, m2 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&p->d_K, m2 * sizeof(double))) != hipSuccess) {
+        (void)hipFree(p->d_anchorbar);
+        (void)hipFree(p->d_tailbar);
+        (void)hipFree(p->d_vout);
+        (void)hipFree(p->d_partial);
+        (void)hipFree(p->d_B);
+        p->d_anchorbar = p->d_tailbar = p->d_vout = p->d_partial = p->d_B = p->d_K = nullptr;
+        return fail(GS_ENOMEM, std::string("adjoint workspace allocation failed: ") +
+                                   hipGetErrorString(e));
+    }
+    return GS_OK;
+}
+
+template <typename T>
+int score_backward_impl(gs_plan_s *p, const double *X, int64_t n, int m, int64_t ldx,
+                        const T *dscores, int what, double *dX, int64_t lddx, void *stream,
+                        const char *who) {
+    int st = check_common(p, X, n, m, ldx, dX, who);
+    if (st != GS_OK) return st;
+    if (!dscores) return fail(GS_EINVAL, std::string(who) + ": dscores is NULL");
+    if (lddx < m) return fail(GS_EINVAL, std::string(who) + ": lddx < m");
+    if (what != GS_OUT_BIC && what != GS_OUT_RSS)
+        return fail(GS_EINVAL, std::string(who) + ": what must be GS_OUT_BIC or GS_OUT_RSS");
+    if ((st = ensure_workspace(p, n)) != GS_OK) return st;
+    if ((st = ensure_adjoint_workspace(p)) != GS_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if ((st = front_half<T>(p, X, n, m, ldx, s, nullptr)) != GS_OK) return st;
+    hipError_t e = launch_walk_adjoint<T>(p, static_cast<const T *>(p->d_anchor),
+                                          static_cast<const T *>(p->d_tail), dscores,
+                                          p->d_anchorbar, p->d_tailbar, n, what == GS_OUT_BIC, s);
+    if (e != hipSuccess) return hip_fail(e, "walk adjoint launch");
+    if ((e = launch_qr_adjoint_chain(p, p->d_r0, p->d_anchorbar, p->d_tailbar, p->d_vout,
+                                     p->d_partial, p->d_B, p->d_K, X, n, ldx, dX, lddx, s)) !=
+        hipSuccess)
+        return hip_fail(e, "QR adjoint launch");
+    if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return GS_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int gs_score_backward(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx,
+                      const float *dscores, int what, double *dX, int64_t lddx, void *stream) {
+    return score_backward_impl<float>(p, X, n, m, ldx, dscores, what, dX, lddx, stream,
+                                      "gs_score_backward");
+}
+
+int gs_score_backward_f64(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx,
+                          const double *dscores, int what, double *dX, int64_t lddx, void *stream) {
+    return score_backward_impl<double>(p, X, n, m, ldx, dscores, what, dX, lddx, stream,
+                                       "gs_score_backward_f64");
+}
+
 
 void gs_plan_destroy(gs_plan_t *p) {
     if (!p) return;

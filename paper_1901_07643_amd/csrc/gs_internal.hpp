@@ -37,6 +37,13 @@ struct gs_plan_s {
     void *d_anchor = nullptr;    // nseg x k x 32 (float or double)
     void *d_tail = nullptr;      // nseg x 32
     int *d_status = nullptr;
+    // adjoint workspace (allocated on the first backward call)
+    double *d_anchorbar = nullptr;  // nseg x k x 32
+    double *d_tailbar = nullptr;    // nseg x 32
+    double *d_vout = nullptr;       // nseg x m x m
+    double *d_partial = nullptr;    // chunks x m x m
+    double *d_B = nullptr;          // m x m
+    double *d_K = nullptr;          // m x m
     hipStream_t last_stream = nullptr;
     hipEvent_t done = nullptr;
 
@@ -73,5 +80,16 @@ hipError_t launch_walk_f32(const gs_plan_s *p, const float *anchor, const float 
                            int64_t n, bool bic, hipStream_t s);
 hipError_t launch_walk_f64(const gs_plan_s *p, const double *anchor, const double *tail,
                            double *out, int64_t n, bool bic, hipStream_t s);
+
+// Adjoint (adjoint.hip)
+template <typename T>
+hipError_t launch_walk_adjoint(const gs_plan_s *p, const T *anchor, const T *tail, const T *dscores,
+                               double *anchorbar, double *tailbar, int64_t n, bool bic,
+                               hipStream_t s);
+int64_t adjoint_partial_chunks(int64_t nseg);
+hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const double *anchorbar,
+                                   const double *tailbar, double *vout, double *partial, double *B,
+                                   double *K, const double *X, int64_t n, int64_t ldx, double *dX,
+                                   int64_t lddx, hipStream_t s);
 
 }  // namespace gs

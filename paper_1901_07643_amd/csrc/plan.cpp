@@ -61,8 +61,8 @@ int build_program(gs_plan_s *p) {
     for (int i = 0; i < q; ++i) mu[i] = ks + i;
     int z = q;
     uint32_t omask = (q == 0) ? 0u : ((1u << q) - 1u);
-    auto put = [&](int64_t t, uint32_t w1) {
-        p->prog[2 * t] = omask | (uint32_t(z) << 16);
+    auto put = [&](int64_t t, uint32_t w1, uint32_t moved = 0) {
+        p->prog[2 * t] = omask | (uint32_t(z) << 16) | (moved << 21);
         p->prog[2 * t + 1] = w1;
     };
     put(0, 0u);
@@ -82,6 +82,7 @@ int build_program(gs_plan_s *p) {
         if (z == j + 1) return fail(GS_EINVAL, "planner: inner block between swapped pair");
         uint32_t w1 = SubWord::kHasTransition | SubWord::kHasMid | (uint32_t(j) << 2) |
                       (uint32_t(mu[j + 1]) << 8) | (uint32_t(z) << 24);
+        const uint32_t moved = uint32_t(mu[j]);
         std::swap(mu[j], mu[j + 1]);
         if (z == j) {
             const int v = mu[z];
@@ -96,7 +97,7 @@ int build_program(gs_plan_s *p) {
         } else {
             return fail(GS_EINVAL, "planner: swap not adjacent to the inner block");
         }
-        put(t++, w1);
+        put(t++, w1, moved);
     }
     if (t != p->nsub) return fail(GS_EINVAL, "planner: wrong number of sub-walks");
     return GS_OK;
@@ -231,6 +232,7 @@ static int simulate(const gs_plan_s *p, int32_t *counts, int64_t len) {
                     const int pos = j < z ? j : j + ks;
                     if ((j < z) != (j + 1 < z)) return fail(GS_EINVAL, "simulate: straddle");
                     if (order[pos + 1] != piv) return fail(GS_EINVAL, "simulate: mid pivot");
+                    if (order[pos] != int((w0 >> 21) & 31)) return fail(GS_EINVAL, "simulate: mid moved");
                     std::swap(order[pos], order[pos + 1]);
                 }
                 const int v = int((w1 >> 16) & 31);
@@ -265,6 +267,8 @@ static int simulate(const gs_plan_s *p, int32_t *counts, int64_t len) {
                 const int j = fwd ? P.j_f[st] : P.j_r[st];
                 const int piv = fwd ? P.piv_f[st] : P.piv_r[st];
                 if (order[z + j + 1] != piv) return fail(GS_EINVAL, "simulate: inner pivot");
+                if (order[z + j] != (fwd ? P.mov_f[st] : P.mov_r[st]))
+                    return fail(GS_EINVAL, "simulate: inner moved");
                 std::swap(order[z + j], order[z + j + 1]);
                 int mk = 0;
                 for (int i = 0; i <= j; ++i) mk |= 1 << order[z + i];

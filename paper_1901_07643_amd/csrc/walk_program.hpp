@@ -27,9 +27,11 @@ struct InnerProgram {
     static constexpr int NA = N > 0 ? N : 1;
     int j_f[NA];      // forward swap positions (Upsilon(K), 0-based)
     int piv_f[NA];    // variable at position j+1 before the forward swap
+    int mov_f[NA];    // variable at position j before it (it moves to j+1)
     int mask_f[NA];   // prefix set (bitmask of inner labels) created by the swap
     int j_r[NA];      // backward walk: Upsilon(K) reversed
     int piv_r[NA];
+    int mov_r[NA];
     int mask_r[NA];
     int init_f[K + 1];  // prefix sets of the forward start ordering (identity)
     int init_r[K + 1];  // prefix sets of the backward start ordering
@@ -63,6 +65,7 @@ constexpr InnerProgram<K> make_inner_program() {
         const int j = seq[t];
         p.j_f[t] = j;
         p.piv_f[t] = ord[j + 1];
+        p.mov_f[t] = ord[j];
         const int tmp = ord[j];
         ord[j] = ord[j + 1];
         ord[j + 1] = tmp;
@@ -80,6 +83,7 @@ constexpr InnerProgram<K> make_inner_program() {
         const int j = seq[N - 1 - t];
         p.j_r[t] = j;
         p.piv_r[t] = ord[j + 1];
+        p.mov_r[t] = ord[j];
         const int tmp = ord[j];
         ord[j] = ord[j + 1];
         ord[j + 1] = tmp;
@@ -110,6 +114,8 @@ constexpr int Q_MAX = 16;
 //   w0: bits 0..15  set of middle variables in front of the inner block
 //                   (bit p = middle variable with label ks + p)
 //       bits 16..20 z = number of middle variables in front, after the transition
+//       bits 21..25 lane (= label) of the middle variable that the middle swap moves
+//                   from position p to p+1 (used by the adjoint to recover c, s)
 //   w1: bit 0       a transition precedes this sub-walk (t > 0)
 //       bit 1       the transition starts with a swap of two middle variables
 //       bits 2..6   that swap's position p (middle positions p and p+1)
