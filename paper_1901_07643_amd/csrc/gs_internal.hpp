@@ -60,11 +60,44 @@ int hip_fail(hipError_t e, const char *what);
 // Host planner (plan.cpp)
 int build_program(gs_plan_s *p);
 
+// One workgroup of a batched TSQR pass: rows [128 block, 128 block + 128) of A.
+struct TsqrJob {
+    const double *A;
+    int64_t nrows;
+    int64_t lda;
+    double *Rout;  // m x m output of this block
+    int *status;
+    int64_t n_orig;
+    int m;
+    int block;
+    int check_finite;
+    int final_pass;
+};
+
+// One dataset of a batched call (device-side descriptor).  The walk of a batch
+// always uses inner blocks of 5 variables (every dataset has m >= 5).
+struct BatchItem {
+    const double *R0;
+    const void *anchor;  // nseg x k x 32 (float)
+    const void *tail;    // nseg x 32
+    const uint32_t *prog;
+    const int32_t *lane_seg;
+    const int8_t *lane_loc;
+    const int *status;
+    void *out;  // the dataset's score table
+    int m, k, ks, q;
+    int64_t nseg, nsub, nwaves;
+    double row_scale, nlog, lnn;
+};
+constexpr int BATCH_KS = 5;
+
 // Kernel launchers (return hipError_t of the launch)
 // TSQR of X (n x m, row stride ldx) into R0 (m x m, upper, non-negative diagonal).
 hipError_t launch_qr_r0(const double *X, int64_t n, int m, int64_t ldx, double *R0, double *bufA,
                         double *bufB, int *status, hipStream_t s);
 int64_t qr_workspace_elems(int64_t n, int m);
+int tsqr_rows_per_block();
+hipError_t launch_tsqr_batched(const TsqrJob *jobs, int njobs, hipStream_t s);
 
 // Host planner: pack segments into 64-lane waves (plan.cpp).
 int pack_waves(gs_plan_s *p);
@@ -80,6 +113,13 @@ hipError_t launch_walk_f32(const gs_plan_s *p, const float *anchor, const float 
                            int64_t n, bool bic, hipStream_t s);
 hipError_t launch_walk_f64(const gs_plan_s *p, const double *anchor, const double *tail,
                            double *out, int64_t n, bool bic, hipStream_t s);
+
+// Batched launches (one per stage for every dataset of a batch)
+hipError_t launch_walk_batched_f32(const BatchItem *items, const int32_t *wave_item,
+                                   const int32_t *wave_local, int64_t total_waves, bool bic,
+                                   hipStream_t s);
+hipError_t launch_anchors_batched_f32(const BatchItem *items, const int64_t *seg_prefix, int count,
+                                      int64_t total_segs, int mmax, hipStream_t s);
 
 // Adjoint (adjoint.hip)
 template <typename T>
