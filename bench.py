@@ -13,6 +13,11 @@ Prints one JSON line.  Besides the contract fields it carries
   valu          the walk's algorithmic FP32 flops against the FP32 vector peak;
   fp64_walk     the same step with the walk in FP64 (families/s);
   fp32_vs_fp64  max relative RSS difference of the two walks over the whole table;
+  batched       256 bootstrap datasets (m 12..18, n 200..2000) in one graph replay of
+                gs_score_batched, with the autotuned cap on k, against 256 sequential
+                gs_score_all calls with the same plans;
+  adjoint       forward + hand-written backward at m = 14, n = 500 (the loss
+                sum_c logsumexp_S(-BIC));
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -74,6 +79,91 @@ def cpu_baseline(X, m, sample: int, seed: int = 1):
                       f"Householder per family), {dt:.2f} s"}
 
 
+def _event_ms(fn, steps: int, stream) -> float:
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_batched(steps: int, stream):
+    """256 bootstrap resamples: one graph replay per step vs 256 gs_score_all calls."""
+    import torch
+
+    import paper_1901_07643_amd as gs
+    from datagen import bootstrap_batch
+    from paper_1901_07643_amd import tune
+    Xh = bootstrap_batch()
+    shapes = [(X.shape[1], X.shape[0]) for X in Xh]
+    Xs = [torch.as_tensor(X, device="cuda") for X in Xh]
+    outs = [torch.empty(gs.num_families(m), dtype=torch.float32, device="cuda") for m, _ in shapes]
+    cap, cap_ms = tune.tune_batch(shapes, reps=3)
+    ks = tune.batch_k(shapes, cap)
+    b = gs.Batch(shapes, k=ks)
+    b.score(Xs, outs=outs, use_graph=True)  # capture + status check
+    ms_graph = _event_ms(lambda: b.score(Xs, outs=outs, use_graph=True, check_status=False),
+                         steps, stream)
+    ms_eager = _event_ms(lambda: b.score(Xs, outs=outs, use_graph=False, check_status=False),
+                         steps, stream)
+    st = b.status()
+    info = b.info
+    b.close()
+    plans = [gs.Plan(m, k, 5) for (m, _), k in zip(shapes, ks)]
+    seq_steps = max(2, steps // 4)
+
+    def sequential():
+        for X, o, p in zip(Xs, outs, plans):
+            gs.score_all(X, plan=p, out=o, check_status=False)
+    sequential()
+    ms_seq = _event_ms(sequential, seq_steps, stream)
+    for p in plans:
+        if p.status() != gs.GS_OK:
+            raise SystemExit("batched workload: bad device status")
+    fam = info["total_families"]
+    if any(x != gs.GS_OK for x in st):
+        raise SystemExit(f"batched workload: device status {st}")
+    return {"workload": "256 bootstrap resamples, m 12..18, n 200..2000", "families": fam,
+            "value": fam / (ms_graph * 1e-3), "unit": "families/s", "ms_per_step": ms_graph,
+            "eager_ms": ms_eager, "sequential_ms": ms_seq,
+            "sequential_value": fam / (ms_seq * 1e-3), "speedup_vs_sequential": ms_seq / ms_graph,
+            "tuned_k_cap": cap, "cap_ms": {str(k): v for k, v in cap_ms.items()},
+            "waves": info["total_waves"], "segments": info["total_segments"],
+            "walk_waves_per_simd": 5}
+
+
+def bench_adjoint(steps: int, stream):
+    """Forward and backward of the loss sum_c logsumexp_S(-BIC) at m = 14, n = 500 (its
+    parity against the oracle's closed-form gradient is a GPU test)."""
+    import torch
+
+    import paper_1901_07643_amd as gs
+    from datagen import CONFIGS, config_data
+    cfg = CONFIGS["c5_m14_n500"]
+    Xh = config_data("c5_m14_n500")
+    X = torch.as_tensor(Xh, device="cuda")
+    m, n = cfg.m, cfg.n
+    plan = gs.Plan(m)
+    nfam = gs.num_families(m)
+    dX = torch.empty((n, m), dtype=torch.float64, device="cuda")
+    bic = gs.score_all(X, plan=plan)
+    dbic = (-torch.softmax(-bic.view(m, -1).double(), dim=1)).float().reshape(-1).contiguous()
+    gs.score_backward(X, dbic, plan=plan, out=dX)
+    ms_fwd = _event_ms(lambda: gs.score_all(X, plan=plan, out=bic, check_status=False), steps,
+                       stream)
+    ms_bwd = _event_ms(lambda: gs.score_backward(X, dbic, plan=plan, out=dX, check_status=False),
+                       steps, stream)
+    res = {"workload": "c5_m14_n500", "families": nfam, "fwd_ms": ms_fwd, "bwd_ms": ms_bwd,
+           "value": nfam / ((ms_fwd + ms_bwd) * 1e-3), "unit": "families/s (fwd+bwd)",
+           "bwd_over_fwd": ms_bwd / ms_fwd}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +173,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=131072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-walk comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (counter calibration)")
     args = ap.parse_args()
@@ -203,6 +295,16 @@ def main():
         del out64
         torch.cuda.synchronize()
         print(f"# fp64 walk {ms64:.4f} ms/step; max rel RSS fp32 vs fp64 {worst:.3e}",
+              file=sys.stderr, flush=True)
+
+    if not args.no_batched:
+        res["batched"] = bench_batched(args.steps, stream)
+        print(f"# batched: {res['batched']['ms_per_step']:.3f} ms/step graph, "
+              f"{res['batched']['sequential_ms']:.3f} ms sequential, cap k={res['batched']['tuned_k_cap']}",
+              file=sys.stderr, flush=True)
+    if not args.no_adjoint:
+        res["adjoint"] = bench_adjoint(args.steps, stream)
+        print(f"# adjoint: fwd {res['adjoint']['fwd_ms']:.4f} ms, bwd {res['adjoint']['bwd_ms']:.4f} ms",
               file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:

@@ -162,6 +162,48 @@ int gs_set_timing(gs_plan_t *plan, int enable);
  * ms[2] walk kernel, ms[3] whole call (host arrays of 4).  *count = calls averaged. */
 int gs_get_timing(gs_plan_t *plan, double *ms, int64_t *count);
 
+/* ---- Batched scoring: many datasets, one launch per stage -------------------
+ * Sec. 6 splits one walk over processors; a batch runs the walks of many datasets
+ * of different m and n (e.g. bootstrap resamples) side by side: one TSQR launch per
+ * pass over all row blocks of all datasets, one anchor launch over all segments, one
+ * walk launch over all packed waves (longest walk first).  FP32 walk, inner blocks
+ * of 5 variables.  The sequence can be captured once into a hipGraph and replayed. */
+typedef struct gs_batch_s gs_batch_t;
+
+typedef struct {
+    const double *X;  /* device, n x m row-major FP64 (the sizes given at creation) */
+    int64_t ldx;      /* row stride of X, >= m                                       */
+    float *scores;    /* device, m * 2^(m-1) floats, 16-byte aligned, table order    */
+} gs_batch_data_t;
+
+/* Plan a batch of `count` (1..4096) datasets: m[i] in 5..GS_MAX_M, n[i] > m[i]
+ * (host arrays).  k (host array or NULL) selects each dataset's segment size as in
+ * gs_plan_tuned (0 = default).  Host-only work; device memory is allocated on the
+ * first gs_score_batched call. */
+int gs_batch_create(int count, const int *m, const int64_t *n, const int *k, gs_batch_t **out);
+
+/* Free a batch, its device workspace and its graphs (NULL is ignored); waits for
+ * the batch's last enqueued work. */
+void gs_batch_destroy(gs_batch_t *batch);
+
+/* Total packed waves, segments and families of the batch (host outputs, each may be
+ * NULL). */
+int gs_batch_info(const gs_batch_t *batch, int64_t *total_waves, int64_t *total_segments,
+                  int64_t *total_families);
+
+/* Scores of every family of every dataset.  data: host array of `count` entries.
+ * what: GS_OUT_BIC or GS_OUT_RSS.  use_graph != 0 replays a hipGraph captured on the
+ * first such call for this `what` (the kernels read the data pointers from a device
+ * table, so a call with different pointers only rewrites the table, after waiting for
+ * the batch's previous call).  Calls on one batch must not overlap. */
+int gs_score_batched(gs_batch_t *batch, const gs_batch_data_t *data, int what, int use_graph,
+                     void *stream);
+
+/* Wait for the batch's last call; status[i] (host, count entries) gets GS_OK,
+ * GS_ERANK or GS_ENOTFINITE for dataset i.  Returns GS_OK or the status of a failed
+ * dataset. */
+int gs_batch_status(gs_batch_t *batch, int *status);
+
 /* Message for the calling thread's last error ("" if none). */
 const char *gs_last_error(void);
 

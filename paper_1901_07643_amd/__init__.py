@@ -19,11 +19,11 @@ import ctypes
 
 import numpy as np
 
-from ._abi import (GS_EINVAL, GS_ENOTFINITE, GS_ERANK, GS_MAX_M, GS_OK, GS_OUT_BIC, GS_OUT_RSS,
+from ._abi import (BatchData, GS_EINVAL, GS_ENOTFINITE, GS_ERANK, GS_MAX_M, GS_OK, GS_OUT_BIC, GS_OUT_RSS,
                    GivScoreError, PlanInfo, check, last_error, lib)
 
 __all__ = [
-    "Plan", "score_all", "score_backward", "givscore", "GivScore", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
+    "Plan", "Batch", "score_all", "score_backward", "givscore", "GivScore", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
     "GS_OK", "GS_EINVAL", "GS_ERANK", "GS_ENOTFINITE", "GS_MAX_M", "lib", "last_error",
 ]
 
@@ -190,6 +190,88 @@ def score_backward(X, dscores, plan: Plan | None = None, what: str = "bic",
         if check_status:
             check(plan.status())
     return out
+
+
+class Batch:
+    """Many datasets scored together: one launch per stage for the whole batch
+    (gs_score_batched), optionally replayed from a captured hipGraph.
+
+        b = Batch([(m0, n0), (m1, n1), ...])
+        tables = b.score([X0, X1, ...])          # list of float32 device tensors
+    """
+
+    def __init__(self, shapes, k=None):
+        shapes = [(int(m), int(n)) for m, n in shapes]
+        cnt = len(shapes)
+        ms = (ctypes.c_int * cnt)(*[m for m, _ in shapes])
+        ns = (ctypes.c_int64 * cnt)(*[n for _, n in shapes])
+        ks = None if k is None else (ctypes.c_int * cnt)(*(k if hasattr(k, "__len__") else [k] * cnt))
+        h = ctypes.c_void_p()
+        check(lib().gs_batch_create(cnt, ms, ns, ks, ctypes.byref(h)))
+        self._h = h
+        self.shapes = shapes
+        self._keep = None
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("batch destroyed")
+        return self._h
+
+    @property
+    def info(self) -> dict:
+        w, s, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(lib().gs_batch_info(self.handle, ctypes.byref(w), ctypes.byref(s), ctypes.byref(f)))
+        return {"total_waves": w.value, "total_segments": s.value, "total_families": f.value}
+
+    def score(self, Xs, what: str = "bic", outs=None, use_graph: bool = True,
+              check_status: bool = True):
+        """Score tables (float32, FP32 walk) of every dataset in Xs (device float64
+        tensors of the shapes given at creation)."""
+        import torch
+        if len(Xs) != len(self.shapes):
+            raise ValueError("one tensor per dataset")
+        w = {"bic": GS_OUT_BIC, "rss": GS_OUT_RSS}[what]
+        dev = Xs[0].device
+        if outs is None:
+            outs = [torch.empty(num_families(m), dtype=torch.float32, device=dev)
+                    for m, _ in self.shapes]
+        data = (BatchData * len(Xs))()
+        for i, (X, (m, n)) in enumerate(zip(Xs, self.shapes)):
+            nn, mm, ldx = _check_X(X, m)
+            if nn != n or X.device != dev:
+                raise ValueError(f"dataset {i}: expected ({n}, {m}) on {dev}")
+            o = outs[i]
+            if o.dtype != torch.float32 or o.numel() != num_families(m) or not o.is_contiguous():
+                raise ValueError(f"dataset {i}: bad output tensor")
+            data[i].X, data[i].ldx, data[i].scores = X.data_ptr(), ldx, o.data_ptr()
+        with torch.cuda.device(dev):
+            check(lib().gs_score_batched(self.handle, data, w, 1 if use_graph else 0, _stream(dev)))
+            self._keep = (list(Xs), outs)  # the tables hold these pointers
+            if check_status:
+                bad = [(i, c) for i, c in enumerate(self.status()) if c != GS_OK]
+                if bad:
+                    raise GivScoreError(bad[0][1], f"dataset {bad[0][0]} (of {len(bad)} failed)")
+        return outs
+
+    def status(self) -> list[int]:
+        """Wait for the last call; per-dataset GS_OK, GS_ERANK or GS_ENOTFINITE."""
+        st = (ctypes.c_int * len(self.shapes))()
+        r = lib().gs_batch_status(self.handle, st)
+        if r not in (GS_OK, GS_ERANK, GS_ENOTFINITE):
+            check(r)
+        return list(st)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().gs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _make_function():

@@ -32,6 +32,10 @@ class PlanInfo(ctypes.Structure):
     ]
 
 
+class BatchData(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("scores", ctypes.c_void_p)]
+
+
 class GivScoreError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -70,6 +74,13 @@ def lib():
         "gs_sync_status": (i32, [vp]),
         "gs_set_timing": (i32, [vp, i32]),
         "gs_get_timing": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+        "gs_batch_create": (i32, [i32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64),
+                                  ctypes.POINTER(ctypes.c_int), pplan]),
+        "gs_batch_destroy": (None, [vp]),
+        "gs_batch_info": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                ctypes.POINTER(i64)]),
+        "gs_score_batched": (i32, [vp, ctypes.POINTER(BatchData), i32, i32, vp]),
+        "gs_batch_status": (i32, [vp, ctypes.POINTER(ctypes.c_int)]),
         "gs_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -59,6 +59,66 @@ __global__ __launch_bounds__(256) void anchor_kernel(const double *__restrict__ 
     tail[seg * 32 + l] = TO(t);
 }
 
+// Anchors of many datasets in one launch: half-wave h of the launch takes the
+// segment h - seg_prefix[b] of dataset b, seg_prefix[b] <= h < seg_prefix[b+1].
+template <int MM>
+__global__ __launch_bounds__(256) void anchor_batched_kernel(const BatchItem *__restrict__ items,
+                                                             const int64_t *__restrict__ seg_prefix,
+                                                             int count, int64_t total_segs) {
+    __shared__ double piv_col[ANCHOR_HALVES][MM];
+    const int hw = threadIdx.x >> 5;
+    const int c = threadIdx.x & 31;
+    const int64_t gseg = int64_t(blockIdx.x) * ANCHOR_HALVES + hw;
+    const bool ok = gseg < total_segs;
+    int lo = 0, hi = count - 1;  // last b with seg_prefix[b] <= gseg
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_prefix[mid] <= gseg) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchItem &d = items[lo];
+    const int64_t seg = ok ? gseg - seg_prefix[lo] : 0;
+    const uint64_t s = uint64_t(seg);
+    const int dd = __popcll((unsigned long long)s);
+    const int label = ok ? segment_label(s, c, d.m, d.k, d.ks) : -1;
+    double col[MM];
+    segment_qr<MM>(d.R0, ok ? d.m : 0, label, c, col, piv_col[hw]);
+    if (!ok || c < dd || c >= d.m) return;
+    const int l = label < d.k ? label : c - dd;
+    float *an = static_cast<float *>(const_cast<void *>(d.anchor)) + seg * int64_t(d.k) * 32;
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < MM; ++i) {
+        const int r = i - dd;
+        if (r >= 0 && r < d.k) an[r * 32 + l] = float(col[i]);
+        if (r >= d.k) t = fma(col[i], col[i], t);
+    }
+    static_cast<float *>(const_cast<void *>(d.tail))[seg * 32 + l] = float(t);
+}
+
+hipError_t launch_anchors_batched_f32(const BatchItem *items, const int64_t *seg_prefix, int count,
+                                      int64_t total_segs, int mmax, hipStream_t s) {
+    const dim3 grid(unsigned((total_segs + ANCHOR_HALVES - 1) / ANCHOR_HALVES)), block(256);
+    switch ((mmax + 3) / 4 * 4) {
+#define GS_ABAT_CASE(MMV)                                                                      \
+    case MMV:                                                                                  \
+        hipLaunchKernelGGL((anchor_batched_kernel<MMV>), grid, block, 0, s, items, seg_prefix, \
+                           count, total_segs);                                                 \
+        break;
+        GS_ABAT_CASE(4)
+        GS_ABAT_CASE(8)
+        GS_ABAT_CASE(12)
+        GS_ABAT_CASE(16)
+        GS_ABAT_CASE(20)
+        GS_ABAT_CASE(24)
+        GS_ABAT_CASE(28)
+        GS_ABAT_CASE(32)
+#undef GS_ABAT_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename TO>
 hipError_t launch_anchors(const double *R0, int m, int k, int ks, int64_t nseg, TO *anchor, TO *tail,
                           hipStream_t s) {

@@ -174,28 +174,23 @@ constexpr int WALK_WAVES = 4;  // waves per workgroup
 #define WALK_MIN_WAVES 5
 #endif
 
-template <typename T, int KS, bool BIC, int MINW>
-__global__ __launch_bounds__(64 * WALK_WAVES) __attribute__((amdgpu_waves_per_eu(MINW, 8))) void walk_kernel(const T *__restrict__ anchor,
-                                                              const T *__restrict__ tail,
-                                                              const uint32_t *__restrict__ prog,
-                                                              const int32_t *__restrict__ lane_seg,
-                                                              const int8_t *__restrict__ lane_loc,
-                                                              const int *__restrict__ status,
-                                                              T *__restrict__ out, WalkArgs a) {
+// The walk of one wave (wave index wid of its dataset's packed wave table).
+template <typename T, int KS, bool BIC>
+__device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T *__restrict__ tail,
+                                          const uint32_t *__restrict__ prog,
+                                          const int32_t *__restrict__ lane_seg,
+                                          const int8_t *__restrict__ lane_loc,
+                                          const int *__restrict__ status, T *__restrict__ out,
+                                          const WalkArgs &a, int64_t wid, T (*L)[64]) {
     constexpr int N = InnerProgram<KS>::N;
     constexpr int NS = 1 << KS;
-    __shared__ T Lrows[WALK_WAVES][Q_MAX][64];
-
-    const int wave = threadIdx.x >> 6;
     const int lane64 = threadIdx.x & 63;
-    const int64_t wid = int64_t(blockIdx.x) * WALK_WAVES + wave;
     // this lane's segment and its column slot l inside it
     const int32_t segv = wid < a.nwaves ? lane_seg[wid * 64 + lane64] : -1;
     const bool seg_ok = segv >= 0;
     const int lane = seg_ok ? int(lane_loc[wid * 64 + lane64]) : 63;
     const int m = a.m, k = a.k, q = a.q, nout = m - k;
     const int bbase = (lane64 - (seg_ok ? lane : 0)) * 4;  // ds_bpermute address of slot 0
-    T(*L)[64] = Lrows[wave];
     // lanes holding inner slot c of their segment (the pivots of the inner walk)
     uint64_t slot_mask[KS];
 #pragma unroll
@@ -365,6 +360,45 @@ __global__ __launch_bounds__(64 * WALK_WAVES) __attribute__((amdgpu_waves_per_eu
     else run(std::false_type{});
 }
 
+template <typename T, int KS, bool BIC, int MINW>
+__global__ __launch_bounds__(64 * WALK_WAVES) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
+void walk_kernel(const T *__restrict__ anchor, const T *__restrict__ tail,
+                 const uint32_t *__restrict__ prog, const int32_t *__restrict__ lane_seg,
+                 const int8_t *__restrict__ lane_loc, const int *__restrict__ status,
+                 T *__restrict__ out, WalkArgs a) {
+    __shared__ T Lrows[WALK_WAVES][Q_MAX][64];
+    const int wave = threadIdx.x >> 6;
+    const int64_t wid = int64_t(blockIdx.x) * WALK_WAVES + wave;
+    walk_body<T, KS, BIC>(anchor, tail, prog, lane_seg, lane_loc, status, out, a, wid,
+                          Lrows[wave]);
+}
+
+// Many datasets in one launch: wave gw walks wave wave_local[gw] of dataset
+// wave_item[gw] (the host orders the waves longest walk first).
+template <typename T, int KS, bool BIC, int MINW>
+__global__ __launch_bounds__(64 * WALK_WAVES) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
+void walk_batched_kernel(const BatchItem *__restrict__ items, const int32_t *__restrict__ wave_item,
+                         const int32_t *__restrict__ wave_local, int64_t total_waves) {
+    __shared__ T Lrows[WALK_WAVES][Q_MAX][64];
+    const int wave = threadIdx.x >> 6;
+    const int64_t gw = int64_t(blockIdx.x) * WALK_WAVES + wave;
+    if (gw >= total_waves) return;
+    const BatchItem &d = items[wave_item[gw]];
+    WalkArgs a;
+    a.m = d.m;
+    a.k = d.k;
+    a.q = d.q;
+    a.nseg = d.nseg;
+    a.nsub = d.nsub;
+    a.nwaves = d.nwaves;
+    a.row_scale = d.row_scale;
+    a.nlog = d.nlog;
+    a.lnn = d.lnn;
+    walk_body<T, KS, BIC>(static_cast<const T *>(d.anchor), static_cast<const T *>(d.tail), d.prog,
+                          d.lane_seg, d.lane_loc, d.status, static_cast<T *>(d.out), a,
+                          wave_local[gw], Lrows[wave]);
+}
+
 // Register budget: the FP32 kernels with inner blocks up to 5 are held to 96 VGPRs
 // (5 waves per SIMD); the others take what they need.
 template <typename T, int KS>
@@ -402,6 +436,19 @@ static hipError_t launch_walk_t(const gs_plan_s *p, const T *anchor, const T *ta
 #undef GS_WALK_CASE
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_batched_f32(const BatchItem *items, const int32_t *wave_item,
+                                   const int32_t *wave_local, int64_t total_waves, bool bic,
+                                   hipStream_t s) {
+    const dim3 grid(unsigned((total_waves + WALK_WAVES - 1) / WALK_WAVES)), block(64 * WALK_WAVES);
+    if (bic)
+        hipLaunchKernelGGL((walk_batched_kernel<float, 5, true, kMinWaves<float, 5>>), grid, block, 0,
+                           s, items, wave_item, wave_local, total_waves);
+    else
+        hipLaunchKernelGGL((walk_batched_kernel<float, 5, false, kMinWaves<float, 5>>), grid, block,
+                           0, s, items, wave_item, wave_local, total_waves);
     return hipGetLastError();
 }
 

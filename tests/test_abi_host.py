@@ -107,3 +107,46 @@ def test_default_plans(gs):
     for m, k, ks in [(8, 5, 5), (14, 5, 5), (20, 5, 5), (26, 11, 5), (30, 13, 5), (3, 3, 3)]:
         inf = gs.Plan(m).info
         assert (inf["k"], inf["ks"]) == (k, ks)
+
+
+def test_batch_planning_host(gs):
+    """Batch creation is host-only: sizes add up over the per-dataset plans."""
+    from datagen import bootstrap_batch
+    shapes = [(X.shape[1], X.shape[0]) for X in bootstrap_batch(count=32)]
+    b = gs.Batch(shapes)
+    inf = b.info
+    waves = segs = 0
+    for m, _ in shapes:
+        pi = gs.Plan(m, 0, 5).info
+        waves += pi["num_waves"]
+        segs += pi["num_segments"]
+    assert inf == {"total_waves": waves, "total_segments": segs,
+                   "total_families": sum(m * 2 ** (m - 1) for m, _ in shapes)}
+    assert b.status() == [gs.GS_OK] * len(shapes)  # nothing enqueued yet
+    b.close()
+
+
+def test_batch_argument_errors(gs):
+    L = gs.lib()
+    h = ctypes.c_void_p()
+    i32, i64 = ctypes.c_int, ctypes.c_int64
+    for ms, ns in [([4], [100]), ([31], [100]), ([8], [8]), ([8, 9], [100, 5])]:
+        cnt = len(ms)
+        r = L.gs_batch_create(cnt, (i32 * cnt)(*ms), (i64 * cnt)(*ns), None, ctypes.byref(h))
+        assert r == gs.GS_EINVAL, (ms, ns)
+    assert L.gs_batch_create(0, (i32 * 1)(8), (i64 * 1)(100), None, ctypes.byref(h)) == gs.GS_EINVAL
+    # bad k for one dataset
+    assert L.gs_batch_create(1, (i32 * 1)(8), (i64 * 1)(100), (i32 * 1)(3),
+                             ctypes.byref(h)) == gs.GS_EINVAL
+    b = gs.Batch([(8, 100)])
+    fake = ctypes.c_void_p(4096)
+    d = (gs._abi.BatchData * 1)()
+    d[0].X, d[0].ldx, d[0].scores = 4096, 7, 4096  # ldx < m
+    assert L.gs_score_batched(b.handle, d, 0, 0, None) == gs.GS_EINVAL
+    d[0].ldx, d[0].scores = 8, 4100  # misaligned table
+    assert L.gs_score_batched(b.handle, d, 0, 0, None) == gs.GS_EINVAL
+    d[0].scores = 4096
+    assert L.gs_score_batched(b.handle, d, 5, 0, None) == gs.GS_EINVAL  # bad what
+    assert L.gs_score_batched(None, d, 0, 0, None) == gs.GS_EINVAL
+    del fake
+    b.close()

@@ -20,10 +20,10 @@ import torch
 
 import oracle
 from datagen import CONFIGS, config_data, linear_gaussian
+from parity import TOL, assert_bic, assert_rss, bic_tol, sample_indices
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-10, "fp32": 1e-4}
 
 
 @pytest.fixture(scope="module")
@@ -44,30 +44,7 @@ def _run(gs, X, what, precision, plan=None):
     return out
 
 
-def _assert_rss(got, want, tol, label=""):
-    got = np.asarray(got, dtype=np.float64)
-    assert np.isfinite(got).all(), f"{label}: unwritten or non-finite entries"
-    rel = np.abs(got - want) / want
-    worst = int(np.argmax(rel))
-    assert rel.max() <= tol, f"{label}: max rel RSS err {rel.max():.3e} at {worst}"
-    return float(rel.max())
-
-
-def _bic_tol(n, bic, precision):
-    eps = 2.0 ** -23 if precision == "fp32" else 2.0 ** -52
-    t = n * TOL[precision] + 8 * eps * np.abs(bic)
-    if precision == "fp32":
-        t = t + n * math.log(2) * 2.0 ** -21
-    return t
-
-
-def _assert_bic(got, want, n, precision, label=""):
-    got = np.asarray(got, dtype=np.float64)
-    assert np.isfinite(got).all(), f"{label}: unwritten or non-finite entries"
-    err = np.abs(got - want)
-    tol = _bic_tol(n, want, precision)
-    bad = np.nonzero(err > tol)[0]
-    assert bad.size == 0, f"{label}: {bad.size} BIC entries off, first {bad[:5]} err {err[bad[:5]]}"
+_assert_rss, _assert_bic, _bic_tol = assert_rss, assert_bic, bic_tol
 
 
 # ---------------------------------------------------------------- R0
@@ -122,11 +99,7 @@ def test_whole_table(gs, m, n, k, ks):
 
 # ---------------------------------------------------------------- full sizes, sampled
 
-def _sample(m, count, seed):
-    rng = np.random.default_rng(seed)
-    N = m * 2 ** (m - 1)
-    idx = rng.choice(N, size=count, replace=False)
-    return np.unique(np.concatenate([idx, [0, N - 1, N // 2, 2 ** (m - 1) - 1]])).astype(np.int64)
+_sample = sample_indices
 
 
 @pytest.mark.parametrize("name", ["c2_m20_n1000", "c3_m26_n5000"])
