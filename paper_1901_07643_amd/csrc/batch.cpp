@@ -345,7 +345,7 @@ static hipError_t enqueue_batch(gs_batch_s *b, bool bic, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (size_t p = 0; p < b->pass_off.size(); ++p)
-        if ((e = launch_tsqr_batched(b->d_jobs + b->pass_off[p], b->pass_cnt[p], s)) != hipSuccess)
+        if ((e = launch_tsqr_batched(b->d_jobs + b->pass_off[p], b->pass_cnt[p], b->mmax, s)) != hipSuccess)
             return e;
     if ((e = launch_anchors_batched_f32(items, b->d_seg_prefix, b->count, b->total_segs,
                                         b->mmax, s)) != hipSuccess)

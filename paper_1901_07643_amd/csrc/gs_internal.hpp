@@ -97,7 +97,7 @@ hipError_t launch_qr_r0(const double *X, int64_t n, int m, int64_t ldx, double *
                         double *bufB, int *status, hipStream_t s);
 int64_t qr_workspace_elems(int64_t n, int m);
 int tsqr_rows_per_block();
-hipError_t launch_tsqr_batched(const TsqrJob *jobs, int njobs, hipStream_t s);
+hipError_t launch_tsqr_batched(const TsqrJob *jobs, int njobs, int mmax, hipStream_t s);
 
 // Host planner: pack segments into 64-lane waves (plan.cpp).
 int pack_waves(gs_plan_s *p);
