@@ -34,7 +34,7 @@ struct gs_batch_s {
     std::vector<gs_plan_s *> plans;
     std::vector<int> m;
     std::vector<int64_t> n;
-    int mmax = 0;
+    int mmax = 0, qmax = 0;
     int64_t total_waves = 0, total_segs = 0, total_families = 0;
 
     // host tables
@@ -244,6 +244,7 @@ int gs_batch_create(int count, const int *m, const int64_t *n, const int *k, gs_
         it.nseg = p->nseg;
         it.nsub = p->nsub;
         it.nwaves = p->nwaves;
+        b->qmax = std::max(b->qmax, p->q);
     }
     b->total_segs = b->seg_prefix[count];
     // waves, longest walk (most sub-walks) first
@@ -350,8 +351,8 @@ static hipError_t enqueue_batch(gs_batch_s *b, bool bic, hipStream_t s) {
     if ((e = launch_anchors_batched_f32(items, b->d_seg_prefix, b->count, b->total_segs,
                                         b->mmax, s)) != hipSuccess)
         return e;
-    return launch_walk_batched_f32(items, b->d_wave_item, b->d_wave_local, b->total_waves, bic,
-                                   s);
+    return launch_walk_batched_f32(items, b->d_wave_item, b->d_wave_local, b->total_waves, b->qmax,
+                                   bic, s);
 }
 
 int gs_score_batched(gs_batch_t *b, const gs_batch_data_t *data, int what, int use_graph,

@@ -53,6 +53,15 @@ struct gs_plan_s {
 
 namespace gs {
 
+// Order the LDS accesses of one wave: some lanes write, others read.  Without the
+// fences the compiler may treat the cross-lane exchange as a data race and move
+// the reads ahead of the writes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
@@ -116,8 +125,8 @@ hipError_t launch_walk_f64(const gs_plan_s *p, const double *anchor, const doubl
 
 // Batched launches (one per stage for every dataset of a batch)
 hipError_t launch_walk_batched_f32(const BatchItem *items, const int32_t *wave_item,
-                                   const int32_t *wave_local, int64_t total_waves, bool bic,
-                                   hipStream_t s);
+                                   const int32_t *wave_local, int64_t total_waves, int qmax,
+                                   bool bic, hipStream_t s);
 hipError_t launch_anchors_batched_f32(const BatchItem *items, const int64_t *seg_prefix, int count,
                                       int64_t total_segs, int mmax, hipStream_t s);
 

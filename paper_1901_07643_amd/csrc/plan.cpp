@@ -314,12 +314,12 @@ int gs_plan_tuned(int m, int k, int ks, gs_plan_t **out) {
     if (m < 1 || m > GS_MAX_M) return fail(GS_EINVAL, "gs_plan: m must be in 1..30");
     if (ks == 0) ks = m < 5 ? m : 5;
     if (k == 0) {
-        // at least 2^14 segments when m allows (at m = 26 about five packed waves per
-        // SIMD: the walk's time then hardly depends on k, while the anchors' time
-        // halves with every step of k), and at most 2^13 - 14 Givens steps per
-        // segment: the FP32 walk's rounding error grows with the length of the walk
-        // from its FP64 start
-        k = m - 14;
+        // at least 2^13 segments when m allows (at m = 26, k = 13 leaves about 2.6
+        // packed waves per SIMD; the walk is bound by its table writes, so fewer,
+        // longer segments cost little there and halve the anchor work per step of
+        // k), and at most 2^13 - 14 Givens steps per segment: the FP32 walk's
+        // rounding error grows with the length of the walk from its FP64 start
+        k = m - 13;
         if (k > kDefaultMaxK) k = kDefaultMaxK;
         if (k < ks) k = ks;
     }

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <type_traits>
 
+#include "gs_internal.hpp"
+
 namespace gs {
 
 template <int I, int N, typename Fn>
@@ -15,15 +17,6 @@ __device__ __forceinline__ void static_for_q(Fn &&f) {
         f(std::integral_constant<int, I>{});
         static_for_q<I + 1, N>(f);
     }
-}
-
-// Order the LDS accesses of one wave: one lane writes, the others read.  Without
-// the fences the compiler may treat the cross-lane exchange as a data race and
-// move the reads ahead of the write.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Variable at position c of segment s's ordering

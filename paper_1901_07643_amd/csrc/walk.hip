@@ -169,6 +169,31 @@ __host__ __device__ constexpr int expand_bit(int i, int c) {
     return ((i >> c) << (c + 1)) | (i & ((1 << c) - 1));
 }
 
+// Table lines of the FP32 walk (inner block 5: 32 floats = 128 bytes) go out through
+// an LDS stage: each lane puts its line (8 float4 chunks) and its destination into
+// the stage, then each of 8 store instructions writes 8 whole lines, 8 consecutive
+// lanes and 16 bytes per lane each.  A lane writing its own line spreads each store
+// instruction over 64 cache lines, which HBM absorbs at little more than half the
+// rate of whole lines.  Chunk c of lane o's line sits at Sg[64 c + (o ^ c)], so that
+// both the writes (c fixed, o = lane) and the reads (8 lanes: one line, c = 0..7)
+// hit distinct LDS banks.
+constexpr int STAGE_LINES = 64, STAGE_CHUNKS = 8;
+constexpr int STAGE_BYTES = STAGE_LINES * STAGE_CHUNKS * 16 + STAGE_LINES * 8;
+
+typedef float native_float4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) native_float4 global_float4;
+
+// 16-byte store through a global address-space pointer.  (A flat store would also
+// count as an LDS operation, and every later wait for LDS would wait for it.)
+__device__ __forceinline__ void global_store16(uint64_t dst, const float4 &v) {
+    native_float4 w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    *reinterpret_cast<global_float4 *>(dst) = w;
+}
+
 constexpr int WALK_WAVES = 4;  // waves per workgroup
 #ifndef WALK_MIN_WAVES
 #define WALK_MIN_WAVES 5
@@ -181,7 +206,8 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
                                           const int32_t *__restrict__ lane_seg,
                                           const int8_t *__restrict__ lane_loc,
                                           const int *__restrict__ status, T *__restrict__ out,
-                                          const WalkArgs &a, int64_t wid, T (*L)[64]) {
+                                          const WalkArgs &a, int64_t wid, T (*L)[64],
+                                          float4 *__restrict__ Sg, uint64_t *__restrict__ Dg) {
     constexpr int N = InnerProgram<KS>::N;
     constexpr int NS = 1 << KS;
     const int lane64 = threadIdx.x & 63;
@@ -327,24 +353,65 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
 
         // write this sub-walk's table lines
         const uint64_t Shi = Fbits | (uint64_t(omask) << KS);
-        const int64_t cbase = int64_t(label) << (m - 1);
-        if (cls == 1) {
-            constexpr int NH = NS / 2;
-            T h[NH];
-            static_for<0, NH>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                T val = o[expand_bit(i, 0)];
-                static_for<1, KS>([&](auto cc) {
-                    constexpr int c = decltype(cc)::value;
-                    val = select_lanes(slot_mask[c], o[expand_bit(i, c)], val);
-                });
-                h[i] = val;
+        const int lb = label < 0 ? 0 : label;
+        const int64_t cbase = int64_t(lb) << (m - 1);
+        const bool child = cls == 3 || (cls == 2 && !((omask >> (lane - KS)) & 1u));
+        const uint64_t low = Shi & ((uint64_t(1) << lb) - 1);
+        const uint64_t high = (Shi >> (lb + 1)) << lb;
+        constexpr int NH = NS / 2;
+        // inner child c (slot c) writes the entries without its own bit
+        auto inner_entry = [&](auto ic) -> T {
+            constexpr int i = decltype(ic)::value;
+            T val = o[expand_bit(i, 0)];
+            static_for<1, KS>([&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                val = select_lanes(slot_mask[c], o[expand_bit(i, c)], val);
             });
-            store_line<NH>(out + cbase + int64_t(Shi >> 1), h);
-        } else if (cls == 3 || (cls == 2 && !((omask >> (lane - KS)) & 1u))) {
-            const uint64_t low = Shi & ((uint64_t(1) << label) - 1);
-            const uint64_t high = (Shi >> (label + 1)) << label;
-            store_line<NS>(out + cbase + int64_t(low | high), o);
+            return val;
+        };
+        if constexpr (std::is_same_v<T, float> && KS == 5) {
+            wave_lds_sync();  // the previous sub-walk's stage reads are done
+            if (cls == 1) {
+                static_for<0, NH / 4>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    Sg[c * STAGE_LINES + (lane64 ^ c)] =
+                        make_float4(inner_entry(std::integral_constant<int, 4 * c>{}),
+                                    inner_entry(std::integral_constant<int, 4 * c + 1>{}),
+                                    inner_entry(std::integral_constant<int, 4 * c + 2>{}),
+                                    inner_entry(std::integral_constant<int, 4 * c + 3>{}));
+                });
+                Dg[lane64] = reinterpret_cast<uint64_t>(out + cbase + int64_t(Shi >> 1)) | (NH / 4);
+            } else {
+                static_for<0, NS / 4>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    Sg[c * STAGE_LINES + (lane64 ^ c)] =
+                        make_float4(o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]);
+                });
+                Dg[lane64] =
+                    child ? reinterpret_cast<uint64_t>(out + cbase + int64_t(low | high)) | (NS / 4) : 0;
+            }
+            wave_lds_sync();
+            const int ch = lane64 & 7;
+            uint64_t dd[8];
+            float4 vv[8];
+            static_for<0, 8>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                const int ow = 8 * t + (lane64 >> 3);
+                dd[t] = Dg[ow];
+                vv[t] = Sg[ch * STAGE_LINES + (ow ^ ch)];
+            });
+            static_for<0, 8>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                if (ch < int(dd[t] & 15u)) global_store16((dd[t] & ~uint64_t(15)) + uint64_t(ch) * 16, vv[t]);
+            });
+        } else {
+            if (cls == 1) {
+                T h[NH];
+                static_for<0, NH>([&](auto ic) { h[decltype(ic)::value] = inner_entry(ic); });
+                store_line<NH>(out + cbase + int64_t(Shi >> 1), h);
+            } else if (child) {
+                store_line<NS>(out + cbase + int64_t(low | high), o);
+            }
         }
     };
     auto run = [&](auto gc) {
@@ -360,17 +427,31 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
     else run(std::false_type{});
 }
 
+template <typename T, int KS>
+__host__ __device__ constexpr size_t walk_stage_bytes() {
+    return (std::is_same_v<T, float> && KS == 5) ? size_t(STAGE_BYTES) : 0;
+}
+template <typename T, int KS>
+__host__ __device__ constexpr size_t walk_wave_lds(int q) {
+    return walk_stage_bytes<T, KS>() + size_t(q > 0 ? q : 1) * 64 * sizeof(T);
+}
+
 template <typename T, int KS, bool BIC, int MINW>
 __global__ __launch_bounds__(64 * WALK_WAVES) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void walk_kernel(const T *__restrict__ anchor, const T *__restrict__ tail,
                  const uint32_t *__restrict__ prog, const int32_t *__restrict__ lane_seg,
                  const int8_t *__restrict__ lane_loc, const int *__restrict__ status,
                  T *__restrict__ out, WalkArgs a) {
-    __shared__ T Lrows[WALK_WAVES][Q_MAX][64];
+    // per wave: the FP32 line stage (inner block 5), then q middle rows of 64 entries
+    extern __shared__ float4 lds_walk[];
     const int wave = threadIdx.x >> 6;
     const int64_t wid = int64_t(blockIdx.x) * WALK_WAVES + wave;
+    char *base = reinterpret_cast<char *>(lds_walk) + wave * walk_wave_lds<T, KS>(a.q);
+    constexpr size_t stage = walk_stage_bytes<T, KS>();
+    float4 *Sg = reinterpret_cast<float4 *>(base);
+    uint64_t *Dg = reinterpret_cast<uint64_t *>(base + STAGE_LINES * STAGE_CHUNKS * 16);
     walk_body<T, KS, BIC>(anchor, tail, prog, lane_seg, lane_loc, status, out, a, wid,
-                          Lrows[wave]);
+                          reinterpret_cast<T(*)[64]>(base + stage), Sg, Dg);
 }
 
 // Many datasets in one launch: wave gw walks wave wave_local[gw] of dataset
@@ -378,11 +459,15 @@ void walk_kernel(const T *__restrict__ anchor, const T *__restrict__ tail,
 template <typename T, int KS, bool BIC, int MINW>
 __global__ __launch_bounds__(64 * WALK_WAVES) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void walk_batched_kernel(const BatchItem *__restrict__ items, const int32_t *__restrict__ wave_item,
-                         const int32_t *__restrict__ wave_local, int64_t total_waves) {
-    __shared__ T Lrows[WALK_WAVES][Q_MAX][64];
+                         const int32_t *__restrict__ wave_local, int64_t total_waves, int qmax) {
+    extern __shared__ float4 lds_walk[];
     const int wave = threadIdx.x >> 6;
     const int64_t gw = int64_t(blockIdx.x) * WALK_WAVES + wave;
     if (gw >= total_waves) return;
+    char *base = reinterpret_cast<char *>(lds_walk) + wave * walk_wave_lds<T, KS>(qmax);
+    constexpr size_t stage = walk_stage_bytes<T, KS>();
+    float4 *Sg = reinterpret_cast<float4 *>(base);
+    uint64_t *Dg = reinterpret_cast<uint64_t *>(base + STAGE_LINES * STAGE_CHUNKS * 16);
     const BatchItem &d = items[wave_item[gw]];
     WalkArgs a;
     a.m = d.m;
@@ -396,13 +481,14 @@ void walk_batched_kernel(const BatchItem *__restrict__ items, const int32_t *__r
     a.lnn = d.lnn;
     walk_body<T, KS, BIC>(static_cast<const T *>(d.anchor), static_cast<const T *>(d.tail), d.prog,
                           d.lane_seg, d.lane_loc, d.status, static_cast<T *>(d.out), a,
-                          wave_local[gw], Lrows[wave]);
+                          wave_local[gw], reinterpret_cast<T(*)[64]>(base + stage), Sg, Dg);
 }
 
-// Register budget: the FP32 kernels with inner blocks up to 5 are held to 96 VGPRs
+// Register budget: the FP32 kernel with inner block 5 is held to 128 VGPRs (4 waves
+// per SIMD; its 8 KB line stage allows no more), smaller inner blocks to 96 VGPRs
 // (5 waves per SIMD); the others take what they need.
 template <typename T, int KS>
-constexpr int kMinWaves = (std::is_same_v<T, float> && KS <= 5) ? WALK_MIN_WAVES : 1;
+constexpr int kMinWaves = !std::is_same_v<T, float> ? 1 : (KS == 5 ? 4 : (KS < 5 ? WALK_MIN_WAVES : 1));
 
 template <typename T, bool BIC>
 static hipError_t launch_walk_t(const gs_plan_s *p, const T *anchor, const T *tail, T *out,
@@ -420,10 +506,11 @@ static hipError_t launch_walk_t(const gs_plan_s *p, const T *anchor, const T *ta
     a.lnn = std::log(dn);
     const dim3 grid(unsigned((p->nwaves + WALK_WAVES - 1) / WALK_WAVES));
     const dim3 block(64 * WALK_WAVES);
+    const size_t lds = WALK_WAVES * (p->ks == 5 ? walk_wave_lds<T, 5>(p->q) : walk_wave_lds<T, 1>(p->q));
     switch (p->ks) {
 #define GS_WALK_CASE(KSV)                                                                   \
     case KSV:                                                                               \
-        hipLaunchKernelGGL((walk_kernel<T, KSV, BIC, kMinWaves<T, KSV>>), grid, block, 0, s, \
+        hipLaunchKernelGGL((walk_kernel<T, KSV, BIC, kMinWaves<T, KSV>>), grid, block, lds, s, \
                            anchor, tail,                                                    \
                            p->d_prog, p->d_lane_seg, p->d_lane_loc, p->d_status, out, a);   \
         break;
@@ -440,15 +527,16 @@ static hipError_t launch_walk_t(const gs_plan_s *p, const T *anchor, const T *ta
 }
 
 hipError_t launch_walk_batched_f32(const BatchItem *items, const int32_t *wave_item,
-                                   const int32_t *wave_local, int64_t total_waves, bool bic,
-                                   hipStream_t s) {
+                                   const int32_t *wave_local, int64_t total_waves, int qmax,
+                                   bool bic, hipStream_t s) {
+    const size_t lds = WALK_WAVES * walk_wave_lds<float, 5>(qmax);
     const dim3 grid(unsigned((total_waves + WALK_WAVES - 1) / WALK_WAVES)), block(64 * WALK_WAVES);
     if (bic)
-        hipLaunchKernelGGL((walk_batched_kernel<float, 5, true, kMinWaves<float, 5>>), grid, block, 0,
-                           s, items, wave_item, wave_local, total_waves);
+        hipLaunchKernelGGL((walk_batched_kernel<float, 5, true, kMinWaves<float, 5>>), grid, block, lds,
+                           s, items, wave_item, wave_local, total_waves, qmax);
     else
         hipLaunchKernelGGL((walk_batched_kernel<float, 5, false, kMinWaves<float, 5>>), grid, block,
-                           0, s, items, wave_item, wave_local, total_waves);
+                           lds, s, items, wave_item, wave_local, total_waves, qmax);
     return hipGetLastError();
 }
 

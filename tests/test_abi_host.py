@@ -104,7 +104,7 @@ def test_plan_covers_every_family_once_large(gs, m, k, ks):
 
 
 def test_default_plans(gs):
-    for m, k, ks in [(8, 5, 5), (14, 5, 5), (20, 6, 5), (26, 12, 5), (30, 13, 5), (3, 3, 3)]:
+    for m, k, ks in [(8, 5, 5), (14, 5, 5), (20, 7, 5), (26, 13, 5), (30, 13, 5), (3, 3, 3)]:
         inf = gs.Plan(m).info
         assert (inf["k"], inf["ks"]) == (k, ks)
 
