@@ -134,7 +134,7 @@ def bench_batched(steps: int, stream):
             "sequential_value": fam / (ms_seq * 1e-3), "speedup_vs_sequential": ms_seq / ms_graph,
             "tuned_k_cap": cap, "cap_ms": {str(k): v for k, v in cap_ms.items()},
             "waves": info["total_waves"], "segments": info["total_segments"],
-            "walk_waves_per_simd": 5}
+            "walk_waves_per_simd": 4}
 
 
 def bench_adjoint(steps: int, stream):
@@ -263,7 +263,7 @@ def main():
                    "plan": {"k": info["k"], "ks": info["ks"], "segments": info["num_segments"]}},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "walk_kernel<float,5,true>",
+                     "traffic": traffic, "kernel": "walk_kernel<float,5,true,4>",
                      "kernel_ms": stage_ms[2]},
         "valu": {"achieved": valu_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                  "frac": valu_tflops / FP32_VECTOR_PEAK_TFLOPS},
