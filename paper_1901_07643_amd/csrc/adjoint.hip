@@ -418,16 +418,20 @@ __global__ __launch_bounds__(64) void anchor_adjoint_kernel(const double *__rest
 }
 
 // partial[ch][e] = sum of vout[seg][e] over the segments of chunk ch (fixed order)
-constexpr int VSUM_CHUNK = 256;
+// Partial sums of the per-segment V blocks: chunk ch (of VSUM_CHUNKS) adds its
+// consecutive segments for one matrix element per thread, in segment order.
+constexpr int VSUM_CHUNKS = 64;
 __global__ __launch_bounds__(256) void sum_v_kernel(const double *__restrict__ vout, int64_t nseg,
-                                                    int mm, double *__restrict__ partial) {
+                                                    int64_t per_chunk, int mm,
+                                                    double *__restrict__ partial) {
     const int64_t ch = blockIdx.x;
-    const int64_t s0 = ch * VSUM_CHUNK, s1 = min(nseg, s0 + VSUM_CHUNK);
-    for (int e = threadIdx.x; e < mm; e += blockDim.x) {
-        double acc = 0.0;
-        for (int64_t sg = s0; sg < s1; ++sg) acc += vout[sg * mm + e];
-        partial[ch * mm + e] = acc;
-    }
+    const int e = int(blockIdx.y) * 256 + int(threadIdx.x);
+    if (e >= mm) return;
+    const int64_t s0 = ch * per_chunk, s1 = min(nseg, s0 + per_chunk);
+    double acc = 0.0;
+#pragma unroll 8
+    for (int64_t sg = s0; sg < s1; ++sg) acc += vout[sg * mm + e];
+    partial[ch * mm + e] = acc;
 }
 
 // B = sum of the partials; R0bar = triu(R0 B); K = R0^-1 copyltu(R0 R0bar^T) R0^-T.
@@ -519,7 +523,7 @@ template hipError_t launch_walk_adjoint<double>(const gs_plan_s *, const double 
                                                 const double *, double *, double *, int64_t, bool,
                                                 hipStream_t);
 
-int64_t adjoint_partial_chunks(int64_t nseg) { return (nseg + VSUM_CHUNK - 1) / VSUM_CHUNK; }
+int64_t adjoint_partial_chunks(int64_t nseg) { return nseg < VSUM_CHUNKS ? nseg : VSUM_CHUNKS; }
 
 hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const double *anchorbar,
                                    const double *tailbar, double *vout, double *partial, double *B,
@@ -548,8 +552,9 @@ hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const d
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nch = adjoint_partial_chunks(p->nseg);
-    hipLaunchKernelGGL(sum_v_kernel, dim3(unsigned(nch)), dim3(256), 0, s, vout, p->nseg, m * m,
-                       partial);
+    const int64_t per_chunk = (p->nseg + nch - 1) / nch;
+    hipLaunchKernelGGL(sum_v_kernel, dim3(unsigned(nch), unsigned((m * m + 255) / 256)), dim3(256), 0,
+                       s, vout, p->nseg, per_chunk, m * m, partial);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     switch (mm) {
 #define GS_FK_CASE(MMV)                                                                       \
