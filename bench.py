@@ -125,6 +125,15 @@ def bench_batched(steps: int, stream):
     for p in plans:
         if p.status() != gs.GS_OK:
             raise SystemExit("batched workload: bad device status")
+    # the plain FP64 walk, dataset after dataset
+    outs64 = [torch.empty(gs.num_families(m), dtype=torch.float64, device="cuda") for m, _ in shapes]
+
+    def sequential64():
+        for X, o, p in zip(Xs, outs64, plans):
+            gs.score_all(X, plan=p, out=o, precision="fp64", check_status=False)
+    sequential64()
+    ms_seq64 = _event_ms(sequential64, 2, stream)
+    del outs64
     fam = info["total_families"]
     if any(x != gs.GS_OK for x in st):
         raise SystemExit(f"batched workload: device status {st}")
@@ -132,6 +141,11 @@ def bench_batched(steps: int, stream):
             "value": fam / (ms_graph * 1e-3), "unit": "families/s", "ms_per_step": ms_graph,
             "eager_ms": ms_eager, "sequential_ms": ms_seq,
             "sequential_value": fam / (ms_seq * 1e-3), "speedup_vs_sequential": ms_seq / ms_graph,
+            "fp64_sequential_value": fam / (ms_seq64 * 1e-3), "fp64_sequential_ms": ms_seq64,
+            "roofline": {"bound": "hbm", "achieved": 4.0 * fam / (ms_graph * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": 4.0 * fam / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "note": "4 B per family written, whole graph replay"},
             "tuned_k_cap": cap, "cap_ms": {str(k): v for k, v in cap_ms.items()},
             "waves": info["total_waves"], "segments": info["total_segments"],
             "walk_waves_per_simd": 4}
@@ -158,9 +172,20 @@ def bench_adjoint(steps: int, stream):
                        stream)
     ms_bwd = _event_ms(lambda: gs.score_backward(X, dbic, plan=plan, out=dX, check_status=False),
                        steps, stream)
+    out64 = torch.empty(nfam, dtype=torch.float64, device="cuda")
+    gs.score_all(X, plan=plan, out=out64, precision="fp64")
+    ms_fwd64 = _event_ms(lambda: gs.score_all(X, plan=plan, out=out64, precision="fp64",
+                                              check_status=False), steps, stream)
+    bwd_bytes = 4.0 * nfam + 8.0 * 2 * n * m  # dscores read once; X read, dX written
     res = {"workload": "c5_m14_n500", "families": nfam, "fwd_ms": ms_fwd, "bwd_ms": ms_bwd,
            "value": nfam / ((ms_fwd + ms_bwd) * 1e-3), "unit": "families/s (fwd+bwd)",
-           "bwd_over_fwd": ms_bwd / ms_fwd}
+           "bwd_over_fwd": ms_bwd / ms_fwd,
+           "fp64_walk_value": nfam / (ms_fwd64 * 1e-3), "fp64_walk_ms": ms_fwd64,
+           "roofline": {"bound": "latency", "achieved": bwd_bytes / (ms_bwd * 1e-3) / 1e9,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": bwd_bytes / (ms_bwd * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "note": "backward: algorithmic bytes (dscores, X, dX) per call; at "
+                                "114,688 families the call is launch and latency bound"}}
     return res
 
 
@@ -244,7 +269,8 @@ def main():
     valu_tflops = alg_flops / walk_s / 1e12
 
     res = {
-        "metric": "families scored/s (BIC) at m=26,n=5000" if args.workload == "c3_m26_n5000"
+        "metric": "families scored/s (BIC) at m=26,n=5000; % FP32 VALU peak; FP32 vs FP64 walk"
+        if args.workload == "c3_m26_n5000"
         else f"families scored/s (BIC) at m={m},n={n}",
         "value": value,
         "unit": "families/s",
