@@ -168,6 +168,25 @@ __device__ __forceinline__ double select_lanes(uint64_t mask, double set, double
 __host__ __device__ constexpr int expand_bit(int i, int c) {
     return ((i >> c) << (c + 1)) | (i & ((1 << c) - 1));
 }
+// the value of expand_bit(i, c) shared by the most c in 0..ks-1 (ties: smallest c)
+__host__ __device__ constexpr int common_expansion(int i, int ks) {
+    int best = expand_bit(i, 0), most = 0;
+    for (int c = 0; c < ks; ++c) {
+        int n = 0;
+        for (int d = 0; d < ks; ++d) n += expand_bit(i, d) == expand_bit(i, c);
+        if (n > most) {
+            most = n;
+            best = expand_bit(i, c);
+        }
+    }
+    return best;
+}
+// c is the smallest slot with its value of expand_bit(i, .)
+__host__ __device__ constexpr bool first_expansion(int i, int c) {
+    for (int d = 0; d < c; ++d)
+        if (expand_bit(i, d) == expand_bit(i, c)) return false;
+    return true;
+}
 
 // Table lines of the FP32 walk (inner block 5: 32 floats = 128 bytes) go out through
 // an LDS stage: each lane puts its line (8 float4 chunks) and its destination into
@@ -360,12 +379,23 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
         const uint64_t high = (Shi >> (lb + 1)) << lb;
         constexpr int NH = NS / 2;
         // inner child c (slot c) writes the entries without its own bit
+        // (one select per distinct candidate: the slots whose entries coincide share
+        // it, and the most common entry needs none)
         auto inner_entry = [&](auto ic) -> T {
             constexpr int i = decltype(ic)::value;
-            T val = o[expand_bit(i, 0)];
-            static_for<1, KS>([&](auto cc) {
+            constexpr int B = common_expansion(i, KS);
+            T val = o[B];
+            static_for<0, KS>([&](auto cc) {
                 constexpr int c = decltype(cc)::value;
-                val = select_lanes(slot_mask[c], o[expand_bit(i, c)], val);
+                constexpr int e = expand_bit(i, c);
+                if constexpr (e != B && first_expansion(i, c)) {
+                    uint64_t msk = 0;
+                    static_for<c, KS>([&](auto dc) {
+                        constexpr int d = decltype(dc)::value;
+                        if constexpr (expand_bit(i, d) == e) msk |= slot_mask[d];
+                    });
+                    val = select_lanes(msk, o[e], val);
+                }
             });
             return val;
         };
