@@ -389,7 +389,7 @@ __global__ __launch_bounds__(64) void anchor_adjoint_kernel(const double *__rest
     const int d = __popcll((unsigned long long)s);
     const int label = ok ? segment_label(s, c, m, k, ks) : -1;
     double col[MM];
-    segment_qr<MM>(R0, m, label, c, col, pcol[hw]);
+    segment_qr<MM>(R0, m, label, c, col, pcol[hw], m);
     double rbar[MM];
 #pragma unroll
     for (int i = 0; i < MM; ++i) rbar[i] = 0.0;

@@ -6,7 +6,9 @@
 // signs) the R of QR(R0 P), an m x m Householder QR instead of an n x m one.
 // Rows of the front variables never change during the walk and are dropped;
 // rows of the back variables never change either and only enter through their
-// squared sums (the "tail" of each back column).
+// squared sums (the "tail" of each back column).  Those sums are the same before
+// and after the reflections of the back columns, so the QR stops after the front
+// and walked columns: d + k of the m Householder steps.
 //
 // One 32-lane half-wave per segment; lane c holds column c of R0 P in registers
 // (rows 0..MM-1, MM >= m).  Each Householder step broadcasts the pivot column
@@ -44,7 +46,8 @@ __global__ __launch_bounds__(256) void anchor_kernel(const double *__restrict__ 
     const int d = __popcll((unsigned long long)s);
     const int label = ok ? segment_label(s, c, m, k, ks) : -1;
     double col[MM];
-    segment_qr<MM>(R0, m, label, c, col, piv_col[hw]);
+    // rows d..d+k-1 and the squared sums below them are all the walk needs
+    segment_qr<MM>(R0, m, label, c, col, piv_col[hw], min(m, d + k));
 
     if (!ok || c < d || c >= m) return;
     const int l = label < k ? label : c - d;  // column slot of this variable
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(256) void anchor_batched_kernel(const BatchItem *__
     const int dd = __popcll((unsigned long long)s);
     const int label = ok ? segment_label(s, c, d.m, d.k, d.ks) : -1;
     double col[MM];
-    segment_qr<MM>(d.R0, ok ? d.m : 0, label, c, col, piv_col[hw]);
+    segment_qr<MM>(d.R0, ok ? d.m : 0, label, c, col, piv_col[hw], ok ? min(d.m, dd + d.k) : 0);
     if (!ok || c < dd || c >= d.m) return;
     const int l = label < d.k ? label : c - dd;
     float *an = static_cast<float *>(const_cast<void *>(d.anchor)) + seg * int64_t(d.k) * 32;
