@@ -69,11 +69,15 @@ __device__ __forceinline__ void segment_qr(const double *__restrict__ R0, int m,
             }
             wave_lds_sync();  // lane j's column is visible to the whole wave
             double v[MM];
-            double tailn = 0.0;
 #pragma unroll
             for (int i = j; i < MM; ++i) v[i] = pc[i];
+            // every lane's product with the pivot column below row j; on the pivot
+            // lane it is the pivot column's squared norm below j, which the other
+            // lanes take from there
+            double dotp = 0.0;
 #pragma unroll
-            for (int i = j + 1; i < MM; ++i) tailn = fma(v[i], v[i], tailn);
+            for (int i = j + 1; i < MM; ++i) dotp = fma(v[i], col[i], dotp);
+            const double tailn = __shfl(dotp, j, 32);
             const double a = v[j];
             const double normx2 = fma(a, a, tailn);
             double alpha = a, f = 0.0, v0 = 0.0;
@@ -82,10 +86,7 @@ __device__ __forceinline__ void segment_qr(const double *__restrict__ R0, int m,
                 alpha = a >= 0.0 ? -nrm : nrm;
                 v0 = a - alpha;
                 const double vtv = fma(v0, v0, tailn);
-                double dot = v0 * col[j];
-#pragma unroll
-                for (int i = j + 1; i < MM; ++i) dot = fma(v[i], col[i], dot);
-                f = 2.0 * dot / vtv;
+                f = 2.0 * fma(v0, col[j], dotp) / vtv;
             }
             if (c == j) {
                 col[j] = alpha;
