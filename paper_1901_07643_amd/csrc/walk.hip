@@ -401,25 +401,40 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
         };
         if constexpr (std::is_same_v<T, float> && KS == 5) {
             wave_lds_sync();  // the previous sub-walk's stage reads are done
-            if (cls == 1) {
-                static_for<0, NH / 4>([&](auto cc) {
+            // One line per lane: its own entries, overridden on inner children's lanes
+            // (slot c) by the entries without bit c; those lanes store 4 chunks only.
+            auto merged_entry = [&](auto ic) -> T {
+                constexpr int i = decltype(ic)::value;
+                T val = o[i];
+                static_for<0, KS>([&](auto cc) {
                     constexpr int c = decltype(cc)::value;
-                    Sg[c * STAGE_LINES + (lane64 ^ c)] =
-                        make_float4(inner_entry(std::integral_constant<int, 4 * c>{}),
-                                    inner_entry(std::integral_constant<int, 4 * c + 1>{}),
-                                    inner_entry(std::integral_constant<int, 4 * c + 2>{}),
-                                    inner_entry(std::integral_constant<int, 4 * c + 3>{}));
+                    constexpr int e = expand_bit(i, c);
+                    if constexpr (e != i && first_expansion(i, c)) {
+                        uint64_t msk = 0;
+                        static_for<c, KS>([&](auto dc) {
+                            constexpr int d = decltype(dc)::value;
+                            if constexpr (expand_bit(i, d) == e) msk |= slot_mask[d];
+                        });
+                        val = select_lanes(msk, o[e], val);
+                    }
                 });
-                Dg[lane64] = reinterpret_cast<uint64_t>(out + cbase + int64_t(Shi >> 1)) | (NH / 4);
-            } else {
-                static_for<0, NS / 4>([&](auto cc) {
-                    constexpr int c = decltype(cc)::value;
+                return val;
+            };
+            static_for<0, NS / 4>([&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                if constexpr (c < NH / 4)
+                    Sg[c * STAGE_LINES + (lane64 ^ c)] =
+                        make_float4(merged_entry(std::integral_constant<int, 4 * c>{}),
+                                    merged_entry(std::integral_constant<int, 4 * c + 1>{}),
+                                    merged_entry(std::integral_constant<int, 4 * c + 2>{}),
+                                    merged_entry(std::integral_constant<int, 4 * c + 3>{}));
+                else
                     Sg[c * STAGE_LINES + (lane64 ^ c)] =
                         make_float4(o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]);
-                });
-                Dg[lane64] =
-                    child ? reinterpret_cast<uint64_t>(out + cbase + int64_t(low | high)) | (NS / 4) : 0;
-            }
+            });
+            const uint64_t inner_dst = reinterpret_cast<uint64_t>(out + cbase + int64_t(Shi >> 1)) | (NH / 4);
+            const uint64_t line_dst = reinterpret_cast<uint64_t>(out + cbase + int64_t(low | high)) | (NS / 4);
+            Dg[lane64] = cls == 1 ? inner_dst : (child ? line_dst : 0);
             wave_lds_sync();
             const int ch = lane64 & 7;
             uint64_t dd[8];
