@@ -435,18 +435,25 @@ __global__ __launch_bounds__(256) void sum_v_kernel(const double *__restrict__ v
 }
 
 // B = sum of the partials; R0bar = triu(R0 B); K = R0^-1 copyltu(R0 R0bar^T) R0^-T.
+constexpr int FINALK_THREADS = 256;
+
 template <int MM>
-__global__ __launch_bounds__(64) void final_k_kernel(const double *__restrict__ R0, int m,
+__global__ __launch_bounds__(FINALK_THREADS) void final_k_kernel(const double *__restrict__ R0, int m,
                                                      const double *__restrict__ partial,
                                                      int64_t nchunks, double *__restrict__ Bout,
                                                      double *__restrict__ K) {
     constexpr int LD = MM + 1;
     __shared__ double Bs[32 * 32];
+    __shared__ double R0s[32 * 32];
     __shared__ double work[3 * MM * LD];
     const int c = threadIdx.x;
     const int mm = m * m;
-    for (int e = c; e < mm; e += 64) {
+    for (int e = c; e < mm; e += FINALK_THREADS) R0s[e] = R0[e];
+    // one entry of B per thread; the chunk loop is unrolled so that its loads are in
+    // flight together (the additions keep their fixed order)
+    for (int e = c; e < mm; e += FINALK_THREADS) {
         double acc = 0.0;
+#pragma unroll 16
         for (int64_t ch = 0; ch < nchunks; ++ch) acc += partial[ch * mm + e];
         Bs[e] = acc;
         Bout[e] = acc;
@@ -456,10 +463,10 @@ __global__ __launch_bounds__(64) void final_k_kernel(const double *__restrict__ 
     double col[MM], rbar[MM];
 #pragma unroll
     for (int i = 0; i < MM; ++i) {
-        col[i] = (c < m) ? (i < m ? R0[i * m + c] : 0.0) : (i == c ? 1.0 : 0.0);
+        col[i] = (c < m) ? (i < m ? R0s[i * m + c] : 0.0) : (i == c ? 1.0 : 0.0);
         double acc = 0.0;
         if (c < m && i < m && i <= c)
-            for (int l = i; l < m; ++l) acc = fma(R0[i * m + l], Bs[l * m + c], acc);
+            for (int l = i; l < m; ++l) acc = fma(R0s[i * m + l], Bs[l * m + c], acc);
         rbar[i] = acc;
     }
     qr_adj_store<MM>(col, rbar, c, work);
@@ -559,7 +566,8 @@ hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const d
     switch (mm) {
 #define GS_FK_CASE(MMV)                                                                       \
     case MMV:                                                                                 \
-        hipLaunchKernelGGL((final_k_kernel<MMV>), dim3(1), dim3(64), 0, s, R0, m, partial, nch, \
+        hipLaunchKernelGGL((final_k_kernel<MMV>), dim3(1), dim3(FINALK_THREADS), 0, s, R0, m,    \
+                           partial, nch,                                                      \
                            B, K);                                                             \
         break;
         GS_FK_CASE(4)
