@@ -66,7 +66,6 @@ struct Arith;
 
 template <>
 struct Arith<float> {
-#ifndef GS_RSQ_RAW
     // hardware 1/sqrt plus one Newton step, so that c^2 + s^2 = 1 to rounding:
     // a biased normalisation error would scale the rows a little at every step
     static __device__ __forceinline__ float rsq(float x) {
@@ -74,9 +73,6 @@ struct Arith<float> {
         const float r = fmaf(-x * y, y, 1.0f);
         return fmaf(0.5f * y, r, y);
     }
-#else
-    static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-#endif
     static __device__ __forceinline__ float tiny() { return 1.17549435e-38f; }
     // BIC from RSS/n: n ln(RSS/n) + cst = (n ln 2) log2(RSS/n) + cst
     static __device__ __forceinline__ float score(float rss, float nlog, float cst) {
@@ -86,7 +82,13 @@ struct Arith<float> {
 
 template <>
 struct Arith<double> {
-    static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+    // hardware 1/sqrt refined by two Newton steps (x >= the smallest normal here)
+    static __device__ __forceinline__ double rsq(double x) {
+        double y = __builtin_amdgcn_rsq(x);
+        y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+        y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+        return y;
+    }
     static __device__ __forceinline__ double tiny() { return 2.2250738585072014e-308; }
     static __device__ __forceinline__ double score(double rss, double nlog, double cst) {
         return fma(nlog, log(rss), cst);
