@@ -62,6 +62,23 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// FP64 1/sqrt(x) and 1/d from the hardware approximations, each refined by two Newton
+// steps (about one ulp; the library's correctly rounded forms cost twice as many
+// instructions).  For normal, finite arguments only.
+__device__ __forceinline__ double rsq_newton(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return y;
+}
+__device__ __forceinline__ double rcp_newton(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+constexpr double GS_DBL_MIN = 2.2250738585072014e-308;
+
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);

@@ -99,11 +99,17 @@ __device__ __forceinline__ void tsqr_block(const double *__restrict__ A, int64_t
             const double rj_c = rowj[par][c];
             const double normx2 = fma(a, a, tailn);
             if (normx2 > 0.0) {
-                const double nrm = sqrt(normx2);
+                // normx2 is the same in every thread, so the branch is uniform
+                double nrm, rvtv;
+                const bool normal = normx2 >= GS_DBL_MIN;
+                if (normal) nrm = normx2 * rsq_newton(normx2);
+                else nrm = sqrt(normx2);
                 const double alpha = a >= 0.0 ? -nrm : nrm;
                 const double v0 = a - alpha;
                 const double vtv = fma(v0, v0, tailn);
-                const double f = (c > j && c < m) ? 2.0 * fma(v0, rj_c, P) / vtv : 0.0;
+                if (normal) rvtv = rcp_newton(vtv);
+                else rvtv = 1.0 / vtv;
+                const double f = (c > j && c < m) ? 2.0 * fma(v0, rj_c, P) * rvtv : 0.0;
 #pragma unroll
                 for (int r = rj + 1; r < QR_RPT; ++r) x[r] = fma(-f, v[r], x[r]);
                 if (g > gj) x[rj] = fma(-f, v[rj], x[rj]);

@@ -82,11 +82,17 @@ __device__ __forceinline__ void segment_qr(const double *__restrict__ R0, int m,
             const double normx2 = fma(a, a, tailn);
             double alpha = a, f = 0.0, v0 = 0.0;
             if (normx2 > 0.0) {
-                const double nrm = sqrt(normx2);
+                // normx2 is the same in every lane of the half-wave (uniform branch)
+                double nrm, rvtv;
+                const bool normal = normx2 >= GS_DBL_MIN;
+                if (normal) nrm = normx2 * rsq_newton(normx2);
+                else nrm = sqrt(normx2);
                 alpha = a >= 0.0 ? -nrm : nrm;
                 v0 = a - alpha;
                 const double vtv = fma(v0, v0, tailn);
-                f = 2.0 * fma(v0, col[j], dotp) / vtv;
+                if (normal) rvtv = rcp_newton(vtv);
+                else rvtv = 1.0 / vtv;
+                f = 2.0 * fma(v0, col[j], dotp) * rvtv;
             }
             if (c == j) {
                 col[j] = alpha;

@@ -82,13 +82,8 @@ struct Arith<float> {
 
 template <>
 struct Arith<double> {
-    // hardware 1/sqrt refined by two Newton steps (x >= the smallest normal here)
-    static __device__ __forceinline__ double rsq(double x) {
-        double y = __builtin_amdgcn_rsq(x);
-        y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-        y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-        return y;
-    }
+    // x >= the smallest normal here (the FP64 walk always takes the guarded path)
+    static __device__ __forceinline__ double rsq(double x) { return rsq_newton(x); }
     static __device__ __forceinline__ double tiny() { return 2.2250738585072014e-308; }
     static __device__ __forceinline__ double score(double rss, double nlog, double cst) {
         return fma(nlog, log(rss), cst);
