@@ -80,13 +80,49 @@ struct Arith<float> {
     }
 };
 
+// ln x for the FP64 scores, branch-free: x = f 2^e with f in [sqrt(1/2), sqrt(2)), and
+// ln f = 2 atanh(u) = 2 u (1 + u^2/3 + u^4/5 + ...), u = (f - 1) / (f + 1), |u| <= 0.1716,
+// summed to u^19 (the rest is below 3e-16); e ln 2 uses ln 2 split into a 32-bit head,
+// so that e times it is exact, and the remainder.  1 / (f + 1) is the hardware
+// reciprocal refined by two Newton steps; the hardware mantissa/exponent split handles
+// subnormal x.  x = 0 (RSS of an exactly rank-deficient prefix) gives -inf, +inf gives
+// +inf and NaN stays NaN.
+__device__ __forceinline__ double ln_score(double x) {
+    constexpr double LN2_HEAD = 0x1.62e42ffp-1;           // ln 2 to 32 bits
+    constexpr double LN2_TAIL = -4.2009150726810846e-11;  // ln 2 - LN2_HEAD
+    double f = __builtin_amdgcn_frexp_mant(x);  // in [1/2, 1) for finite x != 0
+    int e = __builtin_amdgcn_frexp_exp(x);
+    const bool lo = f < 0.70710678118654752;
+    f = lo ? f + f : f;
+    e = lo ? e - 1 : e;
+    const double d = f + 1.0;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    const double u = (f - 1.0) * r;  // f - 1 is exact
+    const double s = u * u;
+    double p = 1.0 / 19;
+    p = fma(p, s, 1.0 / 17);
+    p = fma(p, s, 1.0 / 15);
+    p = fma(p, s, 1.0 / 13);
+    p = fma(p, s, 1.0 / 11);
+    p = fma(p, s, 1.0 / 9);
+    p = fma(p, s, 1.0 / 7);
+    p = fma(p, s, 1.0 / 5);
+    p = fma(p, s, 1.0 / 3);
+    p = fma(p, s, 1.0);
+    const double de = double(e);
+    const double y = fma(de, LN2_HEAD, fma(de, LN2_TAIL, 2.0 * u * p));
+    return x == 0.0 ? -__builtin_inf() : (x == __builtin_inf() ? x : y);
+}
+
 template <>
 struct Arith<double> {
     // x >= the smallest normal here (the FP64 walk always takes the guarded path)
     static __device__ __forceinline__ double rsq(double x) { return rsq_newton(x); }
     static __device__ __forceinline__ double tiny() { return 2.2250738585072014e-308; }
     static __device__ __forceinline__ double score(double rss, double nlog, double cst) {
-        return fma(nlog, log(rss), cst);
+        return fma(nlog, ln_score(rss), cst);
     }
 };
 
