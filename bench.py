@@ -35,7 +35,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-WORKLOADS = {"c3_m26_n5000": "c3_m26_n5000", "c2_m20_n1000": "c2_m20_n1000"}
+WORKLOADS = {"c3_m26_n5000": "c3_m26_n5000", "c2_m20_n1000": "c2_m20_n1000",
+             "c1_m8_n200": "c1_m8_n200"}
 
 
 def runtime_T(m: int) -> int:
