@@ -101,7 +101,8 @@ __device__ __forceinline__ void tsqr_block(const double *__restrict__ A, int64_t
             if (normx2 > 0.0) {
                 // normx2 is the same in every thread, so the branch is uniform
                 double nrm, rvtv;
-                const bool normal = normx2 >= GS_DBL_MIN;
+                // (bounded above too, so that 1 / v^T v <= 1 / normx2 stays a normal number)
+                const bool normal = normx2 >= GS_DBL_MIN && normx2 <= 1e300;
                 if (normal) nrm = normx2 * rsq_newton(normx2);
                 else nrm = sqrt(normx2);
                 const double alpha = a >= 0.0 ? -nrm : nrm;

@@ -84,7 +84,8 @@ __device__ __forceinline__ void segment_qr(const double *__restrict__ R0, int m,
             if (normx2 > 0.0) {
                 // normx2 is the same in every lane of the half-wave (uniform branch)
                 double nrm, rvtv;
-                const bool normal = normx2 >= GS_DBL_MIN;
+                // (bounded above too, so that 1 / v^T v <= 1 / normx2 stays a normal number)
+                const bool normal = normx2 >= GS_DBL_MIN && normx2 <= 1e300;
                 if (normal) nrm = normx2 * rsq_newton(normx2);
                 else nrm = sqrt(normx2);
                 alpha = a >= 0.0 ? -nrm : nrm;

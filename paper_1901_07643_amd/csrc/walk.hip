@@ -84,14 +84,15 @@ struct Arith<float> {
 // ln f = 2 atanh(u) = 2 u (1 + u^2/3 + u^4/5 + ...), u = (f - 1) / (f + 1), |u| <= 0.1716,
 // summed to u^19 (the rest is below 3e-16); e ln 2 uses ln 2 split into a 32-bit head,
 // so that e times it is exact, and the remainder.  1 / (f + 1) is the hardware
-// reciprocal refined by two Newton steps; the hardware mantissa/exponent split handles
-// subnormal x.  x = 0 (RSS of an exactly rank-deficient prefix) gives -inf, +inf gives
-// +inf and NaN stays NaN.
+// reciprocal refined by two Newton steps; a subnormal x is first scaled by 2^64.  x = 0
+// (RSS of an exactly rank-deficient prefix) gives -inf, +inf gives +inf and NaN stays NaN.
 __device__ __forceinline__ double ln_score(double x) {
     constexpr double LN2_HEAD = 0x1.62e42ffp-1;           // ln 2 to 32 bits
     constexpr double LN2_TAIL = -4.2009150726810846e-11;  // ln 2 - LN2_HEAD
-    double f = __builtin_amdgcn_frexp_mant(x);  // in [1/2, 1) for finite x != 0
-    int e = __builtin_amdgcn_frexp_exp(x);
+    const bool sub = x < 2.2250738585072014e-308;
+    const double xs = sub ? x * 0x1p64 : x;
+    double f = __builtin_amdgcn_frexp_mant(xs);  // in [1/2, 1) for finite xs != 0
+    int e = __builtin_amdgcn_frexp_exp(xs) - (sub ? 64 : 0);
     const bool lo = f < 0.70710678118654752;
     f = lo ? f + f : f;
     e = lo ? e - 1 : e;

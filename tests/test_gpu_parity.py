@@ -167,6 +167,23 @@ def test_strided_rows(gs):
     _assert_rss(out, ref, TOL["fp64"], "strided")
 
 
+@pytest.mark.parametrize("scale", [1e150, 1e-150])
+def test_extreme_scales_fp64(gs, scale):
+    """FP64 path on data near the ends of the double range: 1e150 puts the QR steps'
+    squared norms above 1e300 (the library square root and division then replace the
+    refined hardware ones), 1e-150 keeps every value normal but tiny."""
+    m, n = 7, 60
+    X = linear_gaussian(m, n, 0.3, 0.5, 1.5, seed=7) * scale
+    print(f"extreme scale {scale:g}: m={m} n={n}", flush=True)
+    for what, out_kind in (("rss", oracle.OUT_RSS), ("bic", oracle.OUT_BIC)):
+        ref = oracle.score_all(X, out_kind)
+        got = _run(gs, X, what, "fp64").cpu().numpy()
+        if what == "rss":
+            _assert_rss(got, ref, TOL["fp64"], f"scale {scale:g}")
+        else:
+            _assert_bic(got, ref, n, "fp64", f"scale {scale:g}")
+
+
 def test_minimal_samples(gs):
     m = 10
     X = linear_gaussian(m, m + 1, 0.3, 0.5, 1.5, seed=5)
