@@ -49,10 +49,14 @@ typedef struct gs_plan_s gs_plan_t;
 typedef enum {
     GS_OK = 0,
     GS_EINVAL = -1,      /* bad argument: null pointer, size or range            */
-    GS_ERANK = -2,       /* R0 has a (near) zero diagonal: X is rank deficient    */
+    GS_ERANK = -2,       /* X is numerically rank deficient: some column lies
+                            within an angle of n*eps of the span of the others    */
     GS_ENOMEM = -3,      /* device workspace could not be allocated               */
     GS_EHIP = -4,        /* a HIP runtime call failed                             */
-    GS_ENOTFINITE = -5   /* X holds NaN or Inf                                    */
+    GS_ENOTFINITE = -5,  /* X holds NaN or Inf                                    */
+    GS_ERANGE = -6       /* RSS output only: some RSS lies outside the normal range
+                            of the table's type (written as inf, or as a subnormal
+                            or zero that lost relative precision)                 */
 } gs_status;
 
 typedef enum { GS_OUT_BIC = 0, GS_OUT_RSS = 1 } gs_output;
@@ -148,10 +152,20 @@ int gs_score_backward_f64(gs_plan_t *plan, const double *X, int64_t n, int m, in
                           const double *dscores, int what, double *dX, int64_t lddx,
                           void *stream);
 
-/* Wait for the plan's last enqueued work and return GS_OK, GS_ERANK or
- * GS_ENOTFINITE from the device status word of that call (GS_EHIP on a runtime
+/* Wait for the plan's last enqueued work and return GS_OK, GS_ERANK, GS_ENOTFINITE
+ * or GS_ERANGE from the device status word of that call (GS_EHIP on a runtime
  * failure). */
 int gs_sync_status(gs_plan_t *plan);
+
+/* Variance inflation factors of the data of the plan's last call, computed from
+ * its R0: vif[c] = ||x_c||^2 [(X^T X)^-1]_cc = ||x_c||^2 / RSS(c | all other
+ * columns), c = 0..m-1 (host array of m doubles; inf for a singular X).  Waits for
+ * that call.  They bound the sensitivity of every RSS to rounding (no residual of x_c
+ * is smaller than ||x_c||^2 / vif[c]) and so state how far the FP32 walk can be
+ * trusted on this data; the walks are scale free (the columns are equilibrated by
+ * powers of two), so the units of X do not matter.  Not in the paper: its scores are
+ * exact arithmetic. */
+int gs_column_vif(gs_plan_t *plan, double *vif);
 
 /* Per-stage timing with HIP events recorded on the call's stream.  enable != 0
  * starts recording (and clears old records). */

@@ -19,12 +19,12 @@ import ctypes
 
 import numpy as np
 
-from ._abi import (BatchData, GS_EINVAL, GS_ENOTFINITE, GS_ERANK, GS_MAX_M, GS_OK, GS_OUT_BIC, GS_OUT_RSS,
-                   GivScoreError, PlanInfo, check, last_error, lib)
+from ._abi import (BatchData, GS_EINVAL, GS_ENOTFINITE, GS_ERANGE, GS_ERANK, GS_MAX_M, GS_OK,
+                   GS_OUT_BIC, GS_OUT_RSS, GivScoreError, PlanInfo, check, last_error, lib)
 
 __all__ = [
     "Plan", "Batch", "score_all", "score_backward", "givscore", "GivScore", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
-    "GS_OK", "GS_EINVAL", "GS_ERANK", "GS_ENOTFINITE", "GS_MAX_M", "lib", "last_error",
+    "GS_OK", "GS_EINVAL", "GS_ERANK", "GS_ENOTFINITE", "GS_ERANGE", "GS_MAX_M", "lib", "last_error",
 ]
 
 
@@ -80,8 +80,14 @@ class Plan:
 
     def status(self) -> int:
         """Wait for the last call and return its device status code (0, GS_ERANK,
-        GS_ENOTFINITE)."""
+        GS_ENOTFINITE, GS_ERANGE)."""
         return int(lib().gs_sync_status(self.handle))
+
+    def vif(self) -> np.ndarray:
+        """Variance inflation factors of the columns of the last call's data."""
+        out = np.zeros(self.m, dtype=np.float64)
+        check(lib().gs_column_vif(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
 
     def set_timing(self, enable: bool = True):
         check(lib().gs_set_timing(self.handle, 1 if enable else 0))
@@ -255,10 +261,11 @@ class Batch:
         return outs
 
     def status(self) -> list[int]:
-        """Wait for the last call; per-dataset GS_OK, GS_ERANK or GS_ENOTFINITE."""
+        """Wait for the last call; per-dataset GS_OK, GS_ERANK, GS_ENOTFINITE or
+        GS_ERANGE."""
         st = (ctypes.c_int * len(self.shapes))()
         r = lib().gs_batch_status(self.handle, st)
-        if r not in (GS_OK, GS_ERANK, GS_ENOTFINITE):
+        if r not in (GS_OK, GS_ERANK, GS_ENOTFINITE, GS_ERANGE):
             check(r)
         return list(st)
 

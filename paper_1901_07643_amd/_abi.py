@@ -13,13 +13,14 @@ GS_ERANK = -2
 GS_ENOMEM = -3
 GS_EHIP = -4
 GS_ENOTFINITE = -5
+GS_ERANGE = -6
 GS_OUT_BIC = 0
 GS_OUT_RSS = 1
 GS_MAX_M = 30
 
 STATUS_NAMES = {
     GS_OK: "GS_OK", GS_EINVAL: "GS_EINVAL", GS_ERANK: "GS_ERANK", GS_ENOMEM: "GS_ENOMEM",
-    GS_EHIP: "GS_EHIP", GS_ENOTFINITE: "GS_ENOTFINITE",
+    GS_EHIP: "GS_EHIP", GS_ENOTFINITE: "GS_ENOTFINITE", GS_ERANGE: "GS_ERANGE",
 }
 
 
@@ -72,6 +73,7 @@ def lib():
         "gs_score_backward": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
         "gs_score_backward_f64": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
         "gs_sync_status": (i32, [vp]),
+        "gs_column_vif": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
         "gs_set_timing": (i32, [vp, i32]),
         "gs_get_timing": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
         "gs_batch_create": (i32, [i32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64),

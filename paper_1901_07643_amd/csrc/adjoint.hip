@@ -16,6 +16,12 @@
 //   3. final_k_kernel: the reverse rule of X = Q0 R0 with R0bar restricted to the upper
 //      triangle gives Xbar = X K, K = R0^-1 copyltu(R0 R0bar^T) R0^-T.
 //   4. dx_kernel: dX = X K.
+// Like the forward path, every stage works on the column-equilibrated data X D
+// (D = diag(2^-e_c) from the R0 pass): the walk adjoint sees RSS of X D, the anchor
+// QRs are those of R0 D, and the chain ends with d/dX = (d/d(X D)) D, i.e.
+// K = D K_D D.  For RSS scores the cotangent of RSS(c, S) of X D is dscores times
+// 2^(2 e_c); it is carried as 2^(2 (e_c - E)), E = max e_c, and the common factor
+// 2^(2E) is applied to dX at the very end, so no intermediate leaves the range.
 // All reductions are in fixed order (no atomics): the result is bit-reproducible.
 #include <hip/hip_runtime.h>
 
@@ -79,7 +85,16 @@ struct AdjArgs {
     int64_t nseg, nsub;
     double n;
     int bic;
+    const ColStats *stats;
 };
+
+// E = the largest equilibration exponent of the dataset (RSS cotangents are carried
+// relative to 2^(2E))
+__device__ __forceinline__ int max_exp2(const ColStats *st, int m) {
+    int e = st->exp2[0];
+    for (int c = 1; c < m; ++c) e = max(e, st->exp2[c]);
+    return e;
+}
 
 constexpr int ADJ_HALVES = 4;  // segments per 128-thread workgroup
 
@@ -182,6 +197,10 @@ __global__ __launch_bounds__(32 * ADJ_HALVES) void walk_adjoint_kernel(const T *
     const T tl = col_ok ? tail[int64_t(seg) * 32 + lane] : T(0);
     T tlb = T(0);
     const T nn = T(a.n);
+    // RSS scores: d(RSS of X)/d(RSS of X D) = 2^(2 e_c), carried relative to 2^(2E)
+    const T gscale = (a.bic || label < 0)
+                         ? T(1)
+                         : T(ldexp(1.0, 2 * (a.stats->exp2[label] - max_exp2(a.stats, m))));
 
     // 1. replay the walk to its end (rotations only)
     int z = q;
@@ -278,7 +297,7 @@ __global__ __launch_bounds__(32 * ADJ_HALVES) void walk_adjoint_kernel(const T *
         // zero RSS), which must stay 0: a NaN would reach every lane through the sums
         // of the rotation adjoints
         auto gbar = [&](T rss, T g) -> T {
-            return (a.bic && g != T(0)) ? g * nn / rss : g;
+            return (a.bic && g != T(0)) ? g * nn / rss : g * gscale;
         };
         static_for_r<0, N>([&](auto sc) {
             constexpr int st = N - 1 - decltype(sc)::value;
@@ -372,8 +391,9 @@ __global__ __launch_bounds__(32 * ADJ_HALVES) void walk_adjoint_kernel(const T *
 
 // Per segment: V = R^-1 copyltu(R Rbar^T) R^-T of the anchor QR, written in label order.
 template <int MM>
-__global__ __launch_bounds__(64) void anchor_adjoint_kernel(const double *__restrict__ R0, int m,
-                                                            int k, int ks, int64_t nseg,
+__global__ __launch_bounds__(64) void anchor_adjoint_kernel(const double *__restrict__ R0,
+                                                            const ColStats *__restrict__ stats,
+                                                            int m, int k, int ks, int64_t nseg,
                                                             const double *__restrict__ anchorbar,
                                                             const double *__restrict__ tailbar,
                                                             double *__restrict__ vout) {
@@ -389,7 +409,7 @@ __global__ __launch_bounds__(64) void anchor_adjoint_kernel(const double *__rest
     const int d = __popcll((unsigned long long)s);
     const int label = ok ? segment_label(s, c, m, k, ks) : -1;
     double col[MM];
-    segment_qr<MM>(R0, m, label, c, col, pcol[hw], m);
+    segment_qr<MM>(R0, stats->scale, m, label, c, col, pcol[hw], m);
     double rbar[MM];
 #pragma unroll
     for (int i = 0; i < MM; ++i) rbar[i] = 0.0;
@@ -438,17 +458,18 @@ __global__ __launch_bounds__(256) void sum_v_kernel(const double *__restrict__ v
 constexpr int FINALK_THREADS = 256;
 
 template <int MM>
-__global__ __launch_bounds__(FINALK_THREADS) void final_k_kernel(const double *__restrict__ R0, int m,
+__global__ __launch_bounds__(FINALK_THREADS) void final_k_kernel(const double *__restrict__ R0,
+                                                     const ColStats *__restrict__ stats, int m,
                                                      const double *__restrict__ partial,
                                                      int64_t nchunks, double *__restrict__ Bout,
                                                      double *__restrict__ K) {
     constexpr int LD = MM + 1;
     __shared__ double Bs[32 * 32];
-    __shared__ double R0s[32 * 32];
+    __shared__ double R0s[32 * 32];  // R0 D
     __shared__ double work[3 * MM * LD];
     const int c = threadIdx.x;
     const int mm = m * m;
-    for (int e = c; e < mm; e += FINALK_THREADS) R0s[e] = R0[e];
+    for (int e = c; e < mm; e += FINALK_THREADS) R0s[e] = R0[e] * stats->scale[e % m];
     // one entry of B per thread; the chunk loop is unrolled so that its loads are in
     // flight together (the additions keep their fixed order)
     for (int e = c; e < mm; e += FINALK_THREADS) {
@@ -476,20 +497,26 @@ __global__ __launch_bounds__(FINALK_THREADS) void final_k_kernel(const double *_
         for (int p = 0; p < m; ++p) K[c * m + p] = vrow[p];
 }
 
-// dX = X K  (X: n x m, row stride ldx; dX: row stride lddx)
+// dX = (X D) K_D D 2^(2E)  (K_D of the equilibrated problem, D = diag(2^-exp2); X: n x m,
+// row stride ldx; dX: row stride lddx; 2E only for RSS scores)
 __global__ __launch_bounds__(256) void dx_kernel(const double *__restrict__ X, int64_t n, int m,
                                                  int64_t ldx, const double *__restrict__ K,
+                                                 const ColStats *__restrict__ stats, int bic,
                                                  double *__restrict__ dX, int64_t lddx) {
     __shared__ double Ks[32 * 32];
+    __shared__ int ex[32];
+    __shared__ int gexp;
     for (int e = threadIdx.x; e < m * m; e += blockDim.x) Ks[e] = K[e];
+    if (threadIdx.x < m) ex[threadIdx.x] = stats->exp2[threadIdx.x];
+    if (threadIdx.x == 0) gexp = bic ? 0 : 2 * max_exp2(stats, m);
     __syncthreads();
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= n * m) return;
     const int64_t r = idx / m;
     const int j = int(idx - r * m);
     double acc = 0.0;
-    for (int i = 0; i < m; ++i) acc = fma(X[r * ldx + i], Ks[i * m + j], acc);
-    dX[r * lddx + j] = acc;
+    for (int i = 0; i < m; ++i) acc = fma(ldexp(X[r * ldx + i], -ex[i]), Ks[i * m + j], acc);
+    dX[r * lddx + j] = ldexp(acc, gexp - ex[j]);
 }
 
 template <typename T>
@@ -504,6 +531,7 @@ hipError_t launch_walk_adjoint(const gs_plan_s *p, const T *anchor, const T *tai
     a.nsub = p->nsub;
     a.n = double(n);
     a.bic = bic ? 1 : 0;
+    a.stats = p->d_stats;
     const dim3 grid(unsigned((p->nseg + ADJ_HALVES - 1) / ADJ_HALVES)), block(32 * ADJ_HALVES);
     switch (p->ks) {
 #define GS_ADJ_CASE(KSV)                                                                     \
@@ -532,7 +560,8 @@ template hipError_t launch_walk_adjoint<double>(const gs_plan_s *, const double 
 
 int64_t adjoint_partial_chunks(int64_t nseg) { return nseg < VSUM_CHUNKS ? nseg : VSUM_CHUNKS; }
 
-hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const double *anchorbar,
+hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const ColStats *stats,
+                                   bool bic, const double *anchorbar,
                                    const double *tailbar, double *vout, double *partial, double *B,
                                    double *K, const double *X, int64_t n, int64_t ldx, double *dX,
                                    int64_t lddx, hipStream_t s) {
@@ -542,8 +571,8 @@ hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const d
     switch (mm) {
 #define GS_AADJ_CASE(MMV)                                                                        \
     case MMV:                                                                                    \
-        hipLaunchKernelGGL((anchor_adjoint_kernel<MMV>), ag, dim3(64), 0, s, R0, m, p->k, p->ks, \
-                           p->nseg, anchorbar, tailbar, vout);                                   \
+        hipLaunchKernelGGL((anchor_adjoint_kernel<MMV>), ag, dim3(64), 0, s, R0, stats, m, p->k, \
+                           p->ks, p->nseg, anchorbar, tailbar, vout);                            \
         break;
         GS_AADJ_CASE(4)
         GS_AADJ_CASE(8)
@@ -566,7 +595,8 @@ hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const d
     switch (mm) {
 #define GS_FK_CASE(MMV)                                                                       \
     case MMV:                                                                                 \
-        hipLaunchKernelGGL((final_k_kernel<MMV>), dim3(1), dim3(FINALK_THREADS), 0, s, R0, m,    \
+        hipLaunchKernelGGL((final_k_kernel<MMV>), dim3(1), dim3(FINALK_THREADS), 0, s, R0, stats, \
+                           m,                                                                 \
                            partial, nch,                                                      \
                            B, K);                                                             \
         break;
@@ -584,7 +614,7 @@ hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const d
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t tot = n * m;
     hipLaunchKernelGGL(dx_kernel, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s, X, n, m, ldx,
-                       K, dX, lddx);
+                       K, stats, bic ? 1 : 0, dX, lddx);
     return hipGetLastError();
 }
 

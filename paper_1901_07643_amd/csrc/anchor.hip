@@ -3,7 +3,10 @@
 // Sec. 6 gives every processor its own initial QRD but not how to form it.  A
 // segment's ordering is [front variables, middle block, inner block, back
 // variables]; since X P = Q0 (R0 P), the R of that ordering equals (up to row
-// signs) the R of QR(R0 P), an m x m Householder QR instead of an n x m one.
+// signs) the R of QR(R0 P), an m x m Householder QR instead of an n x m one.  The
+// columns are equilibrated first (R0 D, D the power-of-two scales of the R0 pass):
+// the walk then scores X D, whose residual sums differ from those of X only by the
+// exact factor 2^(2 exp2[c]) of the child.
 // Rows of the front variables never change during the walk and are dropped;
 // rows of the back variables never change either and only enter through their
 // squared sums (the "tail" of each back column).  Those sums are the same before
@@ -34,8 +37,10 @@ namespace gs {
 constexpr int ANCHOR_HALVES = 8;  // segments per 256-thread workgroup
 
 template <int MM, typename TO>
-__global__ __launch_bounds__(256) void anchor_kernel(const double *__restrict__ R0, int m, int k,
-                                                     int ks, int64_t nseg, TO *__restrict__ anchor,
+__global__ __launch_bounds__(256) void anchor_kernel(const double *__restrict__ R0,
+                                                     const ColStats *__restrict__ stats, int m,
+                                                     int k, int ks, int64_t nseg,
+                                                     TO *__restrict__ anchor,
                                                      TO *__restrict__ tail) {
     __shared__ double piv_col[ANCHOR_HALVES][MM];
     const int hw = threadIdx.x >> 5;
@@ -47,7 +52,7 @@ __global__ __launch_bounds__(256) void anchor_kernel(const double *__restrict__ 
     const int label = ok ? segment_label(s, c, m, k, ks) : -1;
     double col[MM];
     // rows d..d+k-1 and the squared sums below them are all the walk needs
-    segment_qr<MM>(R0, m, label, c, col, piv_col[hw], min(m, d + k));
+    segment_qr<MM>(R0, stats->scale, m, label, c, col, piv_col[hw], min(m, d + k));
 
     if (!ok || c < d || c >= m) return;
     const int l = label < k ? label : c - d;  // column slot of this variable
@@ -85,7 +90,8 @@ __global__ __launch_bounds__(256) void anchor_batched_kernel(const BatchItem *__
     const int dd = __popcll((unsigned long long)s);
     const int label = ok ? segment_label(s, c, d.m, d.k, d.ks) : -1;
     double col[MM];
-    segment_qr<MM>(d.R0, ok ? d.m : 0, label, c, col, piv_col[hw], ok ? min(d.m, dd + d.k) : 0);
+    segment_qr<MM>(d.R0, d.stats->scale, ok ? d.m : 0, label, c, col, piv_col[hw],
+                   ok ? min(d.m, dd + d.k) : 0);
     if (!ok || c < dd || c >= d.m) return;
     const int l = label < d.k ? label : c - dd;
     float *an = static_cast<float *>(const_cast<void *>(d.anchor)) + seg * int64_t(d.k) * 32;
@@ -123,15 +129,15 @@ hipError_t launch_anchors_batched_f32(const BatchItem *items, const int64_t *seg
 }
 
 template <typename TO>
-hipError_t launch_anchors(const double *R0, int m, int k, int ks, int64_t nseg, TO *anchor, TO *tail,
-                          hipStream_t s) {
+hipError_t launch_anchors(const double *R0, const ColStats *stats, int m, int k, int ks,
+                          int64_t nseg, TO *anchor, TO *tail, hipStream_t s) {
     const dim3 grid(unsigned((nseg + ANCHOR_HALVES - 1) / ANCHOR_HALVES)), block(256);
     const int mm = (m + 3) / 4 * 4;
     switch (mm) {
 #define GS_ANCHOR_CASE(MMV)                                                                   \
     case MMV:                                                                                 \
-        hipLaunchKernelGGL((anchor_kernel<MMV, TO>), grid, block, 0, s, R0, m, k, ks, nseg,  \
-                           anchor, tail);                                                     \
+        hipLaunchKernelGGL((anchor_kernel<MMV, TO>), grid, block, 0, s, R0, stats, m, k, ks, \
+                           nseg, anchor, tail);                                               \
         break;
         GS_ANCHOR_CASE(4)
         GS_ANCHOR_CASE(8)
@@ -147,9 +153,9 @@ hipError_t launch_anchors(const double *R0, int m, int k, int ks, int64_t nseg, 
     return hipGetLastError();
 }
 
-template hipError_t launch_anchors<float>(const double *, int, int, int, int64_t, float *, float *,
-                                          hipStream_t);
-template hipError_t launch_anchors<double>(const double *, int, int, int, int64_t, double *,
-                                           double *, hipStream_t);
+template hipError_t launch_anchors<float>(const double *, const ColStats *, int, int, int, int64_t,
+                                          float *, float *, hipStream_t);
+template hipError_t launch_anchors<double>(const double *, const ColStats *, int, int, int, int64_t,
+                                           double *, double *, hipStream_t);
 
 }  // namespace gs

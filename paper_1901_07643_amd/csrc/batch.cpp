@@ -21,14 +21,6 @@
 
 using namespace gs;
 
-namespace {
-
-__global__ void zero_ints_kernel(int *p, int n) {
-    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) p[i] = 0;
-}
-
-}  // namespace
-
 struct gs_batch_s {
     int count = 0;
     std::vector<gs_plan_s *> plans;
@@ -55,6 +47,7 @@ struct gs_batch_s {
     double *d_r0 = nullptr, *d_qr = nullptr;
     float *d_anchor = nullptr, *d_tail = nullptr;
     int *d_status = nullptr;
+    ColStats *d_stats = nullptr;
     BatchItem *d_items = nullptr;
     int64_t *d_seg_prefix = nullptr;
     int32_t *d_wave_item = nullptr, *d_wave_local = nullptr;
@@ -87,7 +80,7 @@ void batch_free_device(gs_batch_s *b) {
     b->cap = nullptr;
     b->done = nullptr;
     void *ptrs[] = {b->d_prog, b->d_lane_seg, b->d_lane_loc, b->d_r0, b->d_qr, b->d_anchor,
-                    b->d_tail, b->d_status, b->d_items, b->d_seg_prefix, b->d_wave_item,
+                    b->d_tail, b->d_status, b->d_stats, b->d_items, b->d_seg_prefix, b->d_wave_item,
                     b->d_wave_local, b->d_jobs};
     for (void *p : ptrs) (void)hipFree(p);
     b->d_prog = nullptr;
@@ -96,6 +89,7 @@ void batch_free_device(gs_batch_s *b) {
     b->d_r0 = b->d_qr = nullptr;
     b->d_anchor = b->d_tail = nullptr;
     b->d_status = nullptr;
+    b->d_stats = nullptr;
     b->d_items = nullptr;
     b->d_seg_prefix = nullptr;
     b->d_wave_item = b->d_wave_local = nullptr;
@@ -139,6 +133,7 @@ int batch_ensure_device(gs_batch_s *b) {
         (e = hipMalloc(&b->d_anchor, b->an_total * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&b->d_tail, b->tl_total * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&b->d_status, b->count * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&b->d_stats, b->count * sizeof(ColStats))) != hipSuccess ||
         (e = hipMalloc(&b->d_items, 2 * size_t(b->count) * sizeof(BatchItem))) != hipSuccess ||
         (e = alloc_copy(&b->d_seg_prefix, b->seg_prefix.data(), b->seg_prefix.size() * 8)) !=
             hipSuccess ||
@@ -165,6 +160,7 @@ int batch_ensure_device(gs_batch_s *b) {
         it.lane_seg = b->d_lane_seg + b->lane_off[i] * 64;
         it.lane_loc = b->d_lane_loc + b->lane_off[i] * 64;
         it.status = b->d_status + i;
+        it.stats = b->d_stats + i;
         (void)p;
     }
     // TSQR job pointers into the workspace (pass-0 inputs are filled with the data)
@@ -172,6 +168,7 @@ int batch_ensure_device(gs_batch_s *b) {
         TsqrJob &jb = b->jobs[j];
         const int it = int(reinterpret_cast<intptr_t>(jb.status));  // dataset index, see create
         jb.status = b->d_status + it;
+        jb.stats = b->d_stats + it;
         const intptr_t rtag = reinterpret_cast<intptr_t>(jb.Rout);
         const intptr_t atag = reinterpret_cast<intptr_t>(jb.A);
         // tags: Rout = -1 -> R0; otherwise offset+1 into d_qr; A = 0 -> X, else offset+1 into d_qr
@@ -286,10 +283,11 @@ int gs_batch_create(int count, const int *m, const int64_t *n, const int *k, gs_
                 jb.Rout = final_pass ? reinterpret_cast<double *>(intptr_t(-1))
                                      : reinterpret_cast<double *>(dst + blk * mi * mi);
                 jb.status = reinterpret_cast<int *>(intptr_t(i));
+                jb.stats = nullptr;
                 jb.n_orig = n[i];
                 jb.m = mi;
                 jb.block = int(blk);
-                jb.check_finite = pass == 0;
+                jb.first = pass == 0;
                 jb.final_pass = final_pass;
                 b->jobs.push_back(jb);
                 b->pass0_job_item.push_back(pass == 0 ? i : -1);
@@ -342,9 +340,10 @@ int gs_batch_info(const gs_batch_t *b, int64_t *total_waves, int64_t *total_segm
 // table for BIC comes first in d_items, the one for RSS second.
 static hipError_t enqueue_batch(gs_batch_s *b, bool bic, hipStream_t s) {
     const BatchItem *items = b->d_items + (bic ? 0 : b->count);
-    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(256), 0, s, b->d_status, b->count);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_front_reset(b->d_status, b->d_stats, b->count, s);
     if (e != hipSuccess) return e;
+    if ((e = launch_colmax_batched(b->d_jobs + b->pass_off[0], b->pass_cnt[0], s)) != hipSuccess)
+        return e;
     for (size_t p = 0; p < b->pass_off.size(); ++p)
         if ((e = launch_tsqr_batched(b->d_jobs + b->pass_off[p], b->pass_cnt[p], b->mmax, s)) != hipSuccess)
             return e;
@@ -387,6 +386,7 @@ int gs_score_batched(gs_batch_t *b, const gs_batch_data_t *data, int what, int u
             const double dn = double(b->n[i]);
             it.nlog = dn * 0.6931471805599453;  // the FP32 walk takes log2 in hardware
             it.lnn = std::log(dn);
+            it.nln2 = dn * 0.6931471805599453;
             it.row_scale = 1.0 / std::sqrt(dn);  // BIC: the walk sees RSS / n
             tab[i] = it;
             it.row_scale = 1.0;  // RSS
@@ -443,6 +443,7 @@ int gs_batch_status(gs_batch_t *b, int *status) {
     for (int i = 0; i < b->count; ++i) {
         status[i] = (flags[i] & GS_FLAG_NOTFINITE) ? GS_ENOTFINITE
                     : (flags[i] & GS_FLAG_RANK)    ? GS_ERANK
+                    : (flags[i] & GS_FLAG_RANGE)   ? GS_ERANGE
                                                    : GS_OK;
         if (status[i] != GS_OK) worst = status[i];
     }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <string>
 
@@ -12,10 +13,6 @@
 using namespace gs;
 
 namespace {
-
-__global__ void zero_status_kernel(int *st) {
-    if (threadIdx.x == 0) st[0] = 0;
-}
 
 void free_device(gs_plan_s *p) {
     if (p->done) (void)hipEventDestroy(p->done);
@@ -33,6 +30,8 @@ void free_device(gs_plan_s *p) {
     (void)hipFree(p->d_anchor);
     (void)hipFree(p->d_tail);
     (void)hipFree(p->d_status);
+    (void)hipFree(p->d_stats);
+    p->d_stats = nullptr;
     (void)hipFree(p->d_anchorbar);
     (void)hipFree(p->d_tailbar);
     (void)hipFree(p->d_vout);
@@ -69,7 +68,8 @@ int ensure_workspace(gs_plan_s *p, int64_t n) {
             (e = hipMalloc(&p->d_r0, r0_b)) != hipSuccess ||
             (e = hipMalloc(&p->d_anchor, an_b)) != hipSuccess ||
             (e = hipMalloc(&p->d_tail, tl_b)) != hipSuccess ||
-            (e = hipMalloc(&p->d_status, sizeof(int) * 4)) != hipSuccess) {
+            (e = hipMalloc(&p->d_status, sizeof(int) * 4)) != hipSuccess ||
+            (e = hipMalloc(&p->d_stats, sizeof(ColStats))) != hipSuccess) {
             free_device(p);
             return fail(GS_ENOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));
         }
@@ -79,6 +79,7 @@ int ensure_workspace(gs_plan_s *p, int64_t n) {
             (e = hipMemcpy(p->d_lane_loc, p->lane_loc.data(), ll_b, hipMemcpyHostToDevice)) !=
                 hipSuccess ||
             (e = hipMemset(p->d_status, 0, sizeof(int) * 4)) != hipSuccess ||
+            (e = hipMemset(p->d_stats, 0, sizeof(ColStats))) != hipSuccess ||
             (e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming)) != hipSuccess) {
             free_device(p);
             return hip_fail(e, "workspace initialisation");
@@ -120,13 +121,15 @@ int front_half(gs_plan_s *p, const double *X, int64_t n, int m, int64_t ldx, hip
                hipEvent_t *ev) {
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    hipLaunchKernelGGL(zero_status_kernel, dim3(1), dim3(64), 0, s, p->d_status);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "status reset launch");
-    if ((e = launch_qr_r0(X, n, m, ldx, p->d_r0, p->d_qr_a, p->d_qr_b, p->d_status, s)) != hipSuccess)
+    if ((e = launch_front_reset(p->d_status, p->d_stats, 1, s)) != hipSuccess)
+        return hip_fail(e, "status reset launch");
+    if ((e = launch_qr_r0(X, n, m, ldx, p->d_r0, nullptr, p->d_qr_a, p->d_qr_b, p->d_status,
+                          p->d_stats, s)) != hipSuccess)
         return hip_fail(e, "R0 QR launch");
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    if ((e = launch_anchors<T>(p->d_r0, p->m, p->k, p->ks, p->nseg, static_cast<T *>(p->d_anchor),
-                               static_cast<T *>(p->d_tail), s)) != hipSuccess)
+    if ((e = launch_anchors<T>(p->d_r0, p->d_stats, p->m, p->k, p->ks, p->nseg,
+                               static_cast<T *>(p->d_anchor), static_cast<T *>(p->d_tail), s)) !=
+        hipSuccess)
         return hip_fail(e, "anchor launch");
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     return GS_OK;
@@ -206,7 +209,8 @@ int score_backward_impl(gs_plan_s *p, const double *X, int64_t n, int m, int64_t
                                           static_cast<const T *>(p->d_tail), dscores,
                                           p->d_anchorbar, p->d_tailbar, n, what == GS_OUT_BIC, s);
     if (e != hipSuccess) return hip_fail(e, "walk adjoint launch");
-    if ((e = launch_qr_adjoint_chain(p, p->d_r0, p->d_anchorbar, p->d_tailbar, p->d_vout,
+    if ((e = launch_qr_adjoint_chain(p, p->d_r0, p->d_stats, what == GS_OUT_BIC, p->d_anchorbar,
+                                     p->d_tailbar, p->d_vout,
                                      p->d_partial, p->d_B, p->d_K, X, n, ldx, dX, lddx, s)) !=
         hipSuccess)
         return hip_fail(e, "QR adjoint launch");
@@ -250,10 +254,10 @@ int gs_qr_r0(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx, doubl
     if (st != GS_OK) return st;
     if ((st = ensure_workspace(p, n)) != GS_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(zero_status_kernel, dim3(1), dim3(64), 0, s, p->d_status);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_front_reset(p->d_status, p->d_stats, 1, s);
     if (e != hipSuccess) return hip_fail(e, "status reset launch");
-    if ((e = launch_qr_r0(X, n, m, ldx, R0, p->d_qr_a, p->d_qr_b, p->d_status, s)) != hipSuccess)
+    if ((e = launch_qr_r0(X, n, m, ldx, p->d_r0, R0, p->d_qr_a, p->d_qr_b, p->d_status, p->d_stats,
+                          s)) != hipSuccess)
         return hip_fail(e, "R0 QR launch");
     if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     return GS_OK;
@@ -278,7 +282,23 @@ int gs_sync_status(gs_plan_t *p) {
     if ((e = hipMemcpy(&flags, p->d_status, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(e, "status copy");
     if (flags & GS_FLAG_NOTFINITE) return fail(GS_ENOTFINITE, "X holds NaN or Inf");
-    if (flags & GS_FLAG_RANK) return fail(GS_ERANK, "X is rank deficient (R0 diagonal ~ 0)");
+    if (flags & GS_FLAG_RANK)
+        return fail(GS_ERANK, "X is (numerically) rank deficient: a column lies within an angle "
+                              "of n*eps of the span of the others");
+    if (flags & GS_FLAG_RANGE)
+        return fail(GS_ERANGE, "an RSS value lies outside the normal range of the output type");
+    return GS_OK;
+}
+
+int gs_column_vif(gs_plan_t *p, double *vif) {
+    if (!p || !vif) return fail(GS_EINVAL, "gs_column_vif: NULL argument");
+    if (p->device < 0) return fail(GS_EINVAL, "gs_column_vif: the plan has not been used yet");
+    hipError_t e = hipEventSynchronize(p->done);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    const char *src = reinterpret_cast<const char *>(p->d_stats) + offsetof(ColStats, vif);
+    if ((e = hipMemcpy(vif, src, sizeof(double) * size_t(p->m),
+                       hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "statistics copy");
     return GS_OK;
 }
 

@@ -14,6 +14,26 @@
 // Device status word bits (OR-ed by kernels).
 #define GS_FLAG_NOTFINITE 1
 #define GS_FLAG_RANK 2
+#define GS_FLAG_GUARD 4  // a Givens pivot pair may be (near) zero: take the guarded steps
+#define GS_FLAG_RANGE 8  // an RSS value left the output type's normal range
+
+// Column statistics of one dataset.  Before the QR, X is scaled by powers of two
+// so that every column's largest magnitude lies in [1/2, 1) (exp0: the column
+// maxima's exponents, INT_MIN until the first block reports); the TSQR then works on
+// X 2^-exp0, whose squares stay inside the double range, and the stored R0 is the R of
+// that matrix.  The last TSQR pass derives the walk's equilibration: scale[c] turns
+// column c of the stored R0 into a column of norm in [1/2, 1), and X D, D =
+// diag(2^-exp2), is the matrix the walk scores.  RSS(c, S) of X is RSS of X D times
+// 2^(2 exp2[c]) (scaling a parent does not change a residual).
+struct ColStats {
+    double scale[32];  // column scale of the stored R0 (a power of two)
+    double vif[32];    // variance inflation factor ||x_c||^2 [(X^T X)^-1]_cc (inf if singular)
+    int exp2[32];      // X D = X 2^-exp2
+    int exp0[32];      // pre-scaling of X before the QR
+};
+// A VIF above this (an angle below 1e-4 rad between a column and the span of the
+// others) makes the walks take the guarded Givens steps.
+constexpr double GS_GUARD_VIF = 1e8;
 
 struct gs_plan_s {
     int m = 0, k = 0, ks = 0, q = 0;
@@ -31,6 +51,7 @@ struct gs_plan_s {
     int32_t *d_lane_seg = nullptr;
     int8_t *d_lane_loc = nullptr;
     double *d_r0 = nullptr;      // m x m
+    ColStats *d_stats = nullptr;  // column statistics of the last call's data
     double *d_qr_a = nullptr;    // TSQR ping-pong buffers
     double *d_qr_b = nullptr;
     int64_t qr_cap = 0;          // elements per TSQR buffer
@@ -93,10 +114,11 @@ struct TsqrJob {
     int64_t lda;
     double *Rout;  // m x m output of this block
     int *status;
+    ColStats *stats;  // the dataset's statistics (pre-scaling read by pass 0, written last)
     int64_t n_orig;
     int m;
     int block;
-    int check_finite;
+    int first;  // pass 0: reads X and applies the pre-scaling
     int final_pass;
 };
 
@@ -104,6 +126,7 @@ struct TsqrJob {
 // always uses inner blocks of 5 variables (every dataset has m >= 5).
 struct BatchItem {
     const double *R0;
+    const ColStats *stats;
     const void *anchor;  // nseg x k x 32 (float)
     const void *tail;    // nseg x 32
     const uint32_t *prog;
@@ -113,17 +136,23 @@ struct BatchItem {
     void *out;  // the dataset's score table
     int m, k, ks, q;
     int64_t nseg, nsub, nwaves;
-    double row_scale, nlog, lnn;
+    double row_scale, nlog, lnn, nln2;
 };
 constexpr int BATCH_KS = 5;
 
 // Kernel launchers (return hipError_t of the launch)
 // TSQR of X (n x m, row stride ldx) into R0 (m x m, upper, non-negative diagonal).
-hipError_t launch_qr_r0(const double *X, int64_t n, int m, int64_t ldx, double *R0, double *bufA,
-                        double *bufB, int *status, hipStream_t s);
+// R0 of X 2^-exp0 goes to R0; with Rtrue != nullptr also the R factor of X itself.
+// The status word and stats->exp0 must have been reset (launch_front_reset).
+hipError_t launch_qr_r0(const double *X, int64_t n, int m, int64_t ldx, double *R0, double *Rtrue,
+                        double *bufA, double *bufB, int *status, ColStats *stats, hipStream_t s);
+// Reset the status words and the pre-scaling exponents of `count` datasets.
+hipError_t launch_front_reset(int *status, ColStats *stats, int count, hipStream_t s);
 int64_t qr_workspace_elems(int64_t n, int m);
 int tsqr_rows_per_block();
 hipError_t launch_tsqr_batched(const TsqrJob *jobs, int njobs, int mmax, hipStream_t s);
+// Column maxima of the data of every pass-0 job (one 128-row block per workgroup).
+hipError_t launch_colmax_batched(const TsqrJob *jobs, int njobs, hipStream_t s);
 
 // Host planner: pack segments into 64-lane waves (plan.cpp).
 int pack_waves(gs_plan_s *p);
@@ -131,8 +160,8 @@ int pack_waves(gs_plan_s *p);
 // Segment anchors: R blocks of every segment from R0, computed in FP64 and stored
 // as T (float for the FP32 walk, double for the FP64 walk).
 template <typename T>
-hipError_t launch_anchors(const double *R0, int m, int k, int ks, int64_t nseg, T *anchor, T *tail,
-                          hipStream_t s);
+hipError_t launch_anchors(const double *R0, const ColStats *stats, int m, int k, int ks,
+                          int64_t nseg, T *anchor, T *tail, hipStream_t s);
 
 // The walk.  T = float or double; writes the full table.
 hipError_t launch_walk_f32(const gs_plan_s *p, const float *anchor, const float *tail, float *out,
@@ -153,7 +182,8 @@ hipError_t launch_walk_adjoint(const gs_plan_s *p, const T *anchor, const T *tai
                                double *anchorbar, double *tailbar, int64_t n, bool bic,
                                hipStream_t s);
 int64_t adjoint_partial_chunks(int64_t nseg);
-hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const double *anchorbar,
+hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const ColStats *stats,
+                                   bool bic, const double *anchorbar,
                                    const double *tailbar, double *vout, double *partial, double *B,
                                    double *K, const double *X, int64_t n, int64_t ldx, double *dX,
                                    int64_t lddx, hipStream_t s);

@@ -4,8 +4,12 @@
 // O(2 n m^2) step of Sec. 1.1.  Here it is a tall-skinny QR: every workgroup
 // triangularises a block of 128 rows by Householder reflections and writes its
 // m x m R; the stacked R blocks are triangularised again by the same code until one
-// block is left.  The last pass makes the diagonal non-negative and checks the rank;
-// the first pass flags non-finite input.
+// block is left.  Before the first pass a column-maximum pass flags non-finite input
+// and finds, per column, the power of two that brings its largest magnitude into
+// [1/2, 1); the first pass applies it, so that no square or sum of squares of the QR
+// leaves the double range whatever the units of X.  The last pass makes the diagonal
+// non-negative, derives the column statistics the later stages use (the walk's
+// power-of-two equilibration, variance inflation factors) and checks the rank.
 //
 // Layout inside a workgroup (256 threads = 8 row groups x 32 columns): thread
 // (g, c) keeps column c of the rows i = g + 8 r, r = 0..15, in registers.  The
@@ -17,6 +21,7 @@
 // between even and odd columns, so one workgroup barrier per column suffices.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <type_traits>
 
@@ -42,11 +47,145 @@ __device__ __forceinline__ double shfl_half(double v, int src) {
     return __shfl(v, src, 32);
 }
 
+// Column statistics (lane c of the first 32 threads handles column c), from the
+// signed R0 of the pre-scaled data X 2^-exp0 in Rl (zero outside the m x m upper
+// triangle):
+//   scale[c] = 2^-e: column c of that R0 times scale[c] has a norm in [1/2, 1), and
+//     exp2[c] = exp0[c] + e: the column of X times 2^-exp2[c] has that norm;
+//   vif[c] = ||x_c||^2 [(R0^T R0)^-1]_cc = ||x_c||^2 / RSS(c | all other columns),
+//     from the rows of (R0 D)^-1 (D = diag(scale)); inf for a singular R0.
+// Rank flag (scale-free): some column within an angle of n eps of the span of the
+// columns before it (r_cc / ||x_c||) or of all others (1 / sqrt(vif)).  The walks take
+// their guarded Givens steps when the rank flag is set or the largest vif exceeds
+// GS_GUARD_VIF; below that every pivot pair of the equilibrated walk is far from
+// zero and from the FP32 underflow threshold.
+template <int MM>
+__device__ __forceinline__ void col_stats(double (*Rl)[QR_MMAX + 1], int m, int64_t n,
+                                          int *__restrict__ status, ColStats *__restrict__ st) {
+    __shared__ double scl[QR_MMAX];
+    __shared__ double Zl[QR_MMAX][QR_MMAX + 1];
+    const int c = threadIdx.x;  // 0..31
+    double sc = 1.0, ns = 0.0;
+    if (c < m) {
+        // the column's norm is at least its largest entry's magnitude, which the
+        // pre-scaling put in [1/2, 1) (a zero column keeps scale 1 and norm 0)
+        double t = 0.0;
+        for (int i = 0; i <= c; ++i) t = fma(Rl[i][c], Rl[i][c], t);
+        int e = 0;
+        if (t > 0.0) {
+            (void)frexp(sqrt(t), &e);
+            sc = ldexp(1.0, -e);
+            ns = ldexp(sqrt(t), -e);
+        }
+        const int e0 = st->exp0[c];
+        st->exp2[c] = (e0 == INT_MIN ? 0 : e0) + e;
+        st->scale[c] = sc;
+    }
+    scl[c] = c < m ? sc : 0.0;
+    wave_lds_sync();
+    // column c of (R0 D)^-1 by back substitution (zero below row c)
+    double z[MM];
+#pragma unroll
+    for (int i = MM - 1; i >= 0; --i) {
+        double v = 0.0;
+        if (i <= c && c < m) {
+            double acc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int l = i + 1; l < MM; ++l) acc = fma(-Rl[i][l] * scl[l], z[l], acc);
+            v = acc / (Rl[i][i] * scl[i]);
+        }
+        z[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < MM; ++i) Zl[c][i] = z[i];
+    wave_lds_sync();
+    double vif = 0.0, dang = 1.0;
+    if (c < m) {
+        double w = 0.0;
+        for (int j = c; j < m; ++j) w = fma(Zl[j][c], Zl[j][c], w);
+        vif = ns * ns * w;
+        if (!(vif < INFINITY)) vif = INFINITY;  // singular: inf or NaN from 0 / 0
+        st->vif[c] = vif;
+        dang = ns > 0.0 ? fabs(Rl[c][c] * sc) / ns : 0.0;
+    }
+    double vmax = vif, dmin = dang;
+#pragma unroll
+    for (int off = 16; off >= 1; off >>= 1) {
+        vmax = fmax(vmax, __shfl_xor(vmax, off, 32));
+        dmin = fmin(dmin, __shfl_xor(dmin, off, 32));
+    }
+    if (c == 0) {
+        const double tau = double(n) * 2.220446049250313e-16;
+        int f = 0;
+        if (!(dmin > tau) || !(vmax * tau * tau < 1.0)) f = GS_FLAG_RANK | GS_FLAG_GUARD;
+        else if (!(vmax < GS_GUARD_VIF)) f = GS_FLAG_GUARD;
+        if (f) atomicOr(status, f);
+    }
+}
+
+// Column maxima of one 128-row block of X: flags non-finite entries and raises
+// exp0[c] to the exponent e of the block's largest |x_ic| (|x| = f 2^e, f in [1/2, 1)).
+__device__ __forceinline__ void colmax_block(const double *__restrict__ A, int64_t nrows, int m,
+                                             int64_t lda, int64_t r0, int *__restrict__ status,
+                                             int *__restrict__ exp0) {
+    __shared__ double red[QR_G][QR_MMAX];
+    const int tid = threadIdx.x, c = tid & 31, g = tid >> 5;
+    const int rows = int(min<int64_t>(QR_BR, nrows - r0));
+    double mx = 0.0;
+    int bad = 0;
+#pragma unroll
+    for (int r = 0; r < QR_RPT; ++r) {
+        const int i = g + QR_G * r;
+        if (i < rows && c < m) {
+            const double v = A[(r0 + i) * lda + c];
+            if (!isfinite(v)) bad = 1;
+            mx = fmax(mx, fabs(v));  // fmax ignores a NaN operand
+        }
+    }
+    if (bad) atomicOr(status, GS_FLAG_NOTFINITE);
+    red[g][c] = mx;
+    __syncthreads();
+    if (g == 0 && c < m) {
+        for (int gg = 1; gg < QR_G; ++gg) mx = fmax(mx, red[gg][c]);
+        if (mx > 0.0 && mx <= 1.7976931348623157e308) {
+            int e = 0;
+            (void)frexp(mx, &e);
+            atomicMax(exp0 + c, e);
+        }
+    }
+}
+
+__global__ __launch_bounds__(QR_THREADS) void colmax_kernel(const double *__restrict__ A,
+                                                            int64_t nrows, int m, int64_t lda,
+                                                            int *__restrict__ status,
+                                                            ColStats *__restrict__ stats) {
+    colmax_block(A, nrows, m, lda, int64_t(blockIdx.x) * QR_BR, status, stats->exp0);
+}
+
+__global__ __launch_bounds__(QR_THREADS) void colmax_batched_kernel(const TsqrJob *__restrict__ jobs,
+                                                                    int njobs) {
+    if (int(blockIdx.x) >= njobs) return;
+    const TsqrJob jb = jobs[blockIdx.x];
+    colmax_block(jb.A, jb.nrows, jb.m, jb.lda, int64_t(jb.block) * QR_BR, jb.status,
+                 jb.stats->exp0);
+}
+
+__global__ void front_reset_kernel(int *__restrict__ status, ColStats *__restrict__ stats,
+                                   int count) {
+    for (int i = int(blockIdx.x * blockDim.x + threadIdx.x); i < count * 32;
+         i += int(gridDim.x * blockDim.x)) {
+        if ((i & 31) == 0) status[i >> 5] = 0;
+        stats[i >> 5].exp0[i & 31] = INT_MIN;
+    }
+}
+
 // One 128-row block: A (nrows x m, row stride lda) rows [r0, r0 + 128) -> Rout (m x m).
+// The first pass (first != 0) reads X and applies the pre-scaling 2^-exp0.
 template <int MM>
 __device__ __forceinline__ void tsqr_block(const double *__restrict__ A, int64_t nrows, int m,
                                            int64_t lda, int64_t r0, double *__restrict__ Rout,
-                                           int *__restrict__ status, int check_finite,
+                                           double *__restrict__ Rtrue, int *__restrict__ status,
+                                           ColStats *__restrict__ stats, int first,
                                            int final_pass, int64_t n_orig) {
     // per column parity: partial dot products of the 8 row groups, row j, pivot entry
     __shared__ double red[2][QR_G][QR_MMAX];
@@ -57,19 +196,19 @@ __device__ __forceinline__ void tsqr_block(const double *__restrict__ A, int64_t
     const int g = tid >> 5;   // row group
     const int rows = int(min<int64_t>(QR_BR, nrows - r0));
 
+    int e0 = 0;
+    if (first && c < m) {
+        const int e = stats->exp0[c];
+        e0 = e == INT_MIN ? 0 : e;  // INT_MIN: an all-zero (or non-finite) column
+    }
     double x[QR_RPT];
-    int bad = 0;
 #pragma unroll
     for (int r = 0; r < QR_RPT; ++r) {
         const int i = g + QR_G * r;
         double v = 0.0;
-        if (i < rows && c < m) {
-            v = A[(r0 + i) * lda + c];
-            if (check_finite && !isfinite(v)) bad = 1;
-        }
-        x[r] = v;
+        if (i < rows && c < m) v = A[(r0 + i) * lda + c];
+        x[r] = first ? ldexp(v, -e0) : v;
     }
-    if (bad) atomicOr(status, GS_FLAG_NOTFINITE);
 
     // Rows past the block's end hold zeros; a column j >= rows then has a zero
     // tail and its step leaves every row unchanged (normx2 = a^2 with a = 0 below the
@@ -133,6 +272,9 @@ __device__ __forceinline__ void tsqr_block(const double *__restrict__ A, int64_t
         const int i = g + QR_G * r;
         if (i < m && c == i) diag[i] = i < rows ? x[r] : 0.0;
     }
+    // the signed R0, zero outside the m x m triangle, for the statistics below
+    __shared__ double Rl[QR_MMAX][QR_MMAX + 1];
+    for (int e = tid; e < QR_MMAX * (QR_MMAX + 1); e += QR_THREADS) (&Rl[0][0])[e] = 0.0;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < QR_RPT; ++r) {
@@ -141,29 +283,29 @@ __device__ __forceinline__ void tsqr_block(const double *__restrict__ A, int64_t
             double val = (i < rows && c >= i) ? x[r] : 0.0;
             if (diag[i] < 0.0) val = -val;
             Rout[i * m + c] = val;
+            Rl[i][c] = val;
+            if (Rtrue) {
+                const int e = stats->exp0[c];
+                Rtrue[i * m + c] = ldexp(val, e == INT_MIN ? 0 : e);
+            }
         }
     }
-    if (tid == 0) {
-        double dmax = 0.0, dmin = INFINITY;
-        for (int r = 0; r < m; ++r) {
-            const double d = fabs(diag[r]);
-            dmax = fmax(dmax, d);
-            dmin = fmin(dmin, d);
-        }
-        const double eps = 2.220446049250313e-16;
-        if (!(dmin > double(n_orig) * eps * dmax)) atomicOr(status, GS_FLAG_RANK);
-    }
+    __syncthreads();
+    if (tid < 32) col_stats<MM>(Rl, m, n_orig, status, stats);
 }
 
 template <int MM>
 __global__ __launch_bounds__(QR_THREADS) void tsqr_block_kernel(const double *__restrict__ A,
                                                                 int64_t nrows, int m, int64_t lda,
                                                                 double *__restrict__ Rout,
+                                                                double *__restrict__ Rtrue,
                                                                 int *__restrict__ status,
-                                                                int check_finite, int final_pass,
+                                                                ColStats *__restrict__ stats,
+                                                                int first, int final_pass,
                                                                 int64_t n_orig) {
     tsqr_block<MM>(A, nrows, m, lda, int64_t(blockIdx.x) * QR_BR,
-                   Rout + int64_t(blockIdx.x) * m * m, status, check_finite, final_pass, n_orig);
+                   Rout + int64_t(blockIdx.x) * m * m, Rtrue, status, stats, first, final_pass,
+                   n_orig);
 }
 
 // Batched passes: one job per workgroup (see TsqrJob); MM covers the largest m.
@@ -172,8 +314,8 @@ __global__ __launch_bounds__(QR_THREADS) void tsqr_batched_kernel(const TsqrJob 
                                                                   int njobs) {
     if (int(blockIdx.x) >= njobs) return;
     const TsqrJob jb = jobs[blockIdx.x];
-    tsqr_block<MM>(jb.A, jb.nrows, jb.m, jb.lda, int64_t(jb.block) * QR_BR, jb.Rout, jb.status,
-                   jb.check_finite, jb.final_pass, jb.n_orig);
+    tsqr_block<MM>(jb.A, jb.nrows, jb.m, jb.lda, int64_t(jb.block) * QR_BR, jb.Rout, nullptr,
+                   jb.status, jb.stats, jb.first, jb.final_pass, jb.n_orig);
 }
 
 int64_t qr_workspace_elems(int64_t n, int m) {
@@ -197,28 +339,50 @@ int tsqr_rows_per_block() { return QR_BR; }
     }
 
 static hipError_t launch_block(const double *A, int64_t rows, int m, int64_t lda, double *Rout,
-                               int *status, int first, int final_pass, int64_t n, int64_t nb,
-                               hipStream_t s) {
+                               double *Rtrue, int *status, ColStats *stats, int first,
+                               int final_pass, int64_t n, int64_t nb, hipStream_t s) {
 #define GS_QR_CASE(MMV)                                                                        \
     case MMV:                                                                                  \
         hipLaunchKernelGGL((tsqr_block_kernel<MMV>), dim3(unsigned(nb)), dim3(QR_THREADS), 0, s, \
-                           A, rows, m, lda, Rout, status, first, final_pass, n);               \
+                           A, rows, m, lda, Rout, Rtrue, status, stats, first, final_pass, n); \
         break;
     GS_QR_SWITCH((m + 3) / 4 * 4, GS_QR_CASE)
 #undef GS_QR_CASE
     return hipGetLastError();
 }
 
-hipError_t launch_qr_r0(const double *X, int64_t n, int m, int64_t ldx, double *R0, double *bufA,
-                        double *bufB, int *status, hipStream_t s) {
+hipError_t launch_front_reset(int *status, ColStats *stats, int count, hipStream_t s) {
+    const int threads = 256, blocks = (count * 32 + threads - 1) / threads;
+    hipLaunchKernelGGL(front_reset_kernel, dim3(unsigned(blocks)), dim3(threads), 0, s, status,
+                       stats, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_colmax_batched(const TsqrJob *jobs, int njobs, hipStream_t s) {
+    hipLaunchKernelGGL(colmax_batched_kernel, dim3(unsigned(njobs)), dim3(QR_THREADS), 0, s, jobs,
+                       njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_qr_r0(const double *X, int64_t n, int m, int64_t ldx, double *R0, double *Rtrue,
+                        double *bufA, double *bufB, int *status, ColStats *stats, hipStream_t s) {
+    {
+        const int64_t nb = (n + QR_BR - 1) / QR_BR;
+        hipLaunchKernelGGL(colmax_kernel, dim3(unsigned(nb)), dim3(QR_THREADS), 0, s, X, n, m, ldx,
+                           status, stats);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const double *src = X;
     int64_t rows = n, lda = ldx;
     double *dst = bufA, *other = bufB;
     int first = 1;
     for (;;) {
         const int64_t nb = (rows + QR_BR - 1) / QR_BR;
-        if (nb == 1) return launch_block(src, rows, m, lda, R0, status, first, 1, n, 1, s);
-        hipError_t e = launch_block(src, rows, m, lda, dst, status, first, 0, n, nb, s);
+        if (nb == 1)
+            return launch_block(src, rows, m, lda, R0, Rtrue, status, stats, first, 1, n, 1, s);
+        hipError_t e =
+            launch_block(src, rows, m, lda, dst, nullptr, status, stats, first, 0, n, nb, s);
         if (e != hipSuccess) return e;
         first = 0;
         src = dst;

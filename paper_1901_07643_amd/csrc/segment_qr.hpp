@@ -46,19 +46,22 @@ __device__ __forceinline__ int segment_label(uint64_t s, int c, int m, int k, in
     return label;
 }
 
-// Householder QR of A = R0 P (R0: m x m row-major, P: the ordering of segment s),
-// one column per lane of a 32-lane half-wave: on return col[i] = R[i][c] for the
-// lane's column c, with a non-negative diagonal.  Lanes c >= m hold unit columns
-// (R is padded with the identity up to MM).  pc: MM doubles of LDS for this half-wave.
+// Householder QR of A = R0 D P (R0: m x m row-major, D = diag(colscale), the
+// power-of-two column equilibration, P: the ordering of segment s), one column per
+// lane of a 32-lane half-wave: on return col[i] = R[i][c] for the lane's column c,
+// with a non-negative diagonal.  Lanes c >= m hold unit columns (R is padded with the
+// identity up to MM).  pc: MM doubles of LDS for this half-wave.
 // With steps < m only the first `steps` reflections are applied: rows 0..steps-1 are
 // then final, and rows steps.. hold, per column, the same sum of squares as the
 // triangular R (the remaining reflections act on those rows alone and keep it).
 template <int MM>
-__device__ __forceinline__ void segment_qr(const double *__restrict__ R0, int m, int label, int c,
-                                           double (&col)[MM], double *pc, int steps) {
+__device__ __forceinline__ void segment_qr(const double *__restrict__ R0,
+                                           const double *__restrict__ colscale, int m, int label,
+                                           int c, double (&col)[MM], double *pc, int steps) {
+    const double sc = label >= 0 ? colscale[label] : 1.0;
 #pragma unroll
     for (int i = 0; i < MM; ++i)
-        col[i] = label >= 0 ? (i < m ? R0[i * m + label] : 0.0) : (i == c ? 1.0 : 0.0);
+        col[i] = label >= 0 ? (i < m ? R0[i * m + label] * sc : 0.0) : (i == c ? 1.0 : 0.0);
     static_for_q<0, MM>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         if (j < steps) {

@@ -33,6 +33,10 @@
 // for an ordering with variable c at position p, RSS(c | first i variables) is
 // the sum of the squares of column c over rows i..p.  Per lane the kernels keep
 // these suffix sums: after a swap at j only the one for row j+1 changes.
+//
+// The walk scores the column-equilibrated data X D (D = diag(2^-e_c), every column
+// norm in [1/2, 1)): RSS(c, S) of X is the walk's value times 2^(2 e_c), exactly (an
+// ldexp), and BIC gains the constant 2 e_c n ln 2 of the child.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -74,6 +78,10 @@ struct Arith<float> {
         return fmaf(0.5f * y, r, y);
     }
     static __device__ __forceinline__ float tiny() { return 1.17549435e-38f; }
+    static __device__ __forceinline__ float huge() { return 3.40282347e+38f; }
+    static __device__ __forceinline__ float ldexp(float x, int e) {
+        return __builtin_amdgcn_ldexpf(x, e);
+    }
     // BIC from RSS/n: n ln(RSS/n) + cst = (n ln 2) log2(RSS/n) + cst
     static __device__ __forceinline__ float score(float rss, float nlog, float cst) {
         return fmaf(nlog, __builtin_amdgcn_logf(rss), cst);
@@ -122,6 +130,10 @@ struct Arith<double> {
     // x >= the smallest normal here (the FP64 walk always takes the guarded path)
     static __device__ __forceinline__ double rsq(double x) { return rsq_newton(x); }
     static __device__ __forceinline__ double tiny() { return 2.2250738585072014e-308; }
+    static __device__ __forceinline__ double huge() { return 1.7976931348623157e+308; }
+    static __device__ __forceinline__ double ldexp(double x, int e) {
+        return __builtin_amdgcn_ldexp(x, e);
+    }
     static __device__ __forceinline__ double score(double rss, double nlog, double cst) {
         return fma(nlog, ln_score(rss), cst);
     }
@@ -150,6 +162,7 @@ struct WalkArgs {
     double row_scale;  // 1/sqrt(n) for BIC (the table then gets RSS/n inside the log), 1 for RSS
     double nlog;       // n ln 2 (FP32 path, log2 in hardware) or n (FP64 path)
     double lnn;        // ln n
+    double nln2;       // n ln 2: BIC of X = BIC of X D + 2 e_c n ln 2
 };
 
 template <int CNT, typename T>
@@ -258,7 +271,8 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
                                           const uint32_t *__restrict__ prog,
                                           const int32_t *__restrict__ lane_seg,
                                           const int8_t *__restrict__ lane_loc,
-                                          const int *__restrict__ status, T *__restrict__ out,
+                                          const int *__restrict__ status,
+                                          const ColStats *__restrict__ stats, T *__restrict__ out,
                                           const WalkArgs &a, int64_t wid, T (*L)[64],
                                           float4 *__restrict__ Sg, uint64_t *__restrict__ Dg) {
     constexpr int N = InnerProgram<KS>::N;
@@ -308,6 +322,10 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
     for (int p = 0; p < q; ++p) L[p][lane64] = seg_ok ? an[p * 32] * rs : T(0);
     const T tl = seg_ok ? tail[int64_t(segv) * 32 + lane] * rs * rs : T(0);
     const T nlog = T(a.nlog), lnn = T(a.lnn);
+    // the child's equilibration exponent: BIC offset, RSS factor 2^(2 e_c)
+    const int ec2 = label >= 0 ? 2 * stats->exp2[label] : 0;
+    const T coff = T(a.nln2 * double(ec2));
+    bool out_of_range = false;  // RSS output only: a value outside the normal range
 
     int z = q;
     // One sub-walk: the transition into it, the inner walk, the table writes.  FWD is
@@ -376,12 +394,19 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
         T cst[KS + 1];
         const int cnt0 = nF + __popc(omask) + 2;
 #pragma unroll
-        for (int u = 0; u <= KS; ++u) cst[u] = T(cnt0 + u) * lnn;
+        for (int u = 0; u <= KS; ++u) cst[u] = fma(T(cnt0 + u), lnn, coff);
 
         T o[NS];
         auto score = [&](T rss, int u) -> T {
-            if constexpr (BIC) return Arith<T>::score(rss, nlog, cst[u]);
-            else return rss;
+            if constexpr (BIC) {
+                return Arith<T>::score(rss, nlog, cst[u]);
+            } else {
+                const T v = Arith<T>::ldexp(rss, ec2);
+                // an overflow, or an underflow of a non-zero residual (to a subnormal or 0)
+                out_of_range = out_of_range || v > Arith<T>::huge() ||
+                               (v < Arith<T>::tiny() && rss != T(0));
+                return v;
+            }
         };
         static_for<0, KS + 1>([&](auto pc) {
             constexpr int pl = decltype(pc)::value;
@@ -500,10 +525,15 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
             else sub_walk(gc, std::false_type{}, w0, w1);
         }
     };
-    // The R0 kernel has flagged a (near) rank-deficient X: only then can a Givens
-    // pivot pair be exactly zero.  The FP64 walk always takes the guarded path.
-    if (std::is_same_v<T, double> || (status[0] & GS_FLAG_RANK)) run(std::true_type{});
+    // The R0 pass has flagged a (near) rank-deficient or very ill-conditioned X: only
+    // then can a Givens pivot pair be (near) zero.  The FP64 walk always takes the
+    // guarded path.
+    if (std::is_same_v<T, double> || (status[0] & GS_FLAG_GUARD)) run(std::true_type{});
     else run(std::false_type{});
+    if constexpr (!BIC) {
+        if (__builtin_amdgcn_ballot_w64(out_of_range && seg_ok) != 0 && lane64 == 0)
+            atomicOr(const_cast<int *>(status), GS_FLAG_RANGE);
+    }
 }
 
 template <typename T, int KS>
@@ -520,7 +550,7 @@ __global__ __launch_bounds__(64 * WALK_WAVES) __attribute__((amdgpu_waves_per_eu
 void walk_kernel(const T *__restrict__ anchor, const T *__restrict__ tail,
                  const uint32_t *__restrict__ prog, const int32_t *__restrict__ lane_seg,
                  const int8_t *__restrict__ lane_loc, const int *__restrict__ status,
-                 T *__restrict__ out, WalkArgs a) {
+                 const ColStats *__restrict__ stats, T *__restrict__ out, WalkArgs a) {
     // per wave: the FP32 line stage (inner block 5), then q middle rows of 64 entries
     extern __shared__ float4 lds_walk[];
     const int wave = threadIdx.x >> 6;
@@ -529,7 +559,7 @@ void walk_kernel(const T *__restrict__ anchor, const T *__restrict__ tail,
     constexpr size_t stage = walk_stage_bytes<T, KS>();
     float4 *Sg = reinterpret_cast<float4 *>(base);
     uint64_t *Dg = reinterpret_cast<uint64_t *>(base + STAGE_LINES * STAGE_CHUNKS * 16);
-    walk_body<T, KS, BIC>(anchor, tail, prog, lane_seg, lane_loc, status, out, a, wid,
+    walk_body<T, KS, BIC>(anchor, tail, prog, lane_seg, lane_loc, status, stats, out, a, wid,
                           reinterpret_cast<T(*)[64]>(base + stage), Sg, Dg);
 }
 
@@ -558,8 +588,9 @@ void walk_batched_kernel(const BatchItem *__restrict__ items, const int32_t *__r
     a.row_scale = d.row_scale;
     a.nlog = d.nlog;
     a.lnn = d.lnn;
+    a.nln2 = d.nln2;
     walk_body<T, KS, BIC>(static_cast<const T *>(d.anchor), static_cast<const T *>(d.tail), d.prog,
-                          d.lane_seg, d.lane_loc, d.status, static_cast<T *>(d.out), a,
+                          d.lane_seg, d.lane_loc, d.status, d.stats, static_cast<T *>(d.out), a,
                           wave_local[gw], reinterpret_cast<T(*)[64]>(base + stage), Sg, Dg);
 }
 
@@ -583,6 +614,7 @@ static hipError_t launch_walk_t(const gs_plan_s *p, const T *anchor, const T *ta
     a.row_scale = BIC ? 1.0 / std::sqrt(dn) : 1.0;
     a.nlog = std::is_same_v<T, float> ? dn * 0.6931471805599453 : dn;
     a.lnn = std::log(dn);
+    a.nln2 = dn * 0.6931471805599453;
     const dim3 grid(unsigned((p->nwaves + WALK_WAVES - 1) / WALK_WAVES));
     const dim3 block(64 * WALK_WAVES);
     const size_t lds = WALK_WAVES * (p->ks == 5 ? walk_wave_lds<T, 5>(p->q) : walk_wave_lds<T, 1>(p->q));
@@ -591,7 +623,8 @@ static hipError_t launch_walk_t(const gs_plan_s *p, const T *anchor, const T *ta
     case KSV:                                                                               \
         hipLaunchKernelGGL((walk_kernel<T, KSV, BIC, kMinWaves<T, KSV>>), grid, block, lds, s, \
                            anchor, tail,                                                    \
-                           p->d_prog, p->d_lane_seg, p->d_lane_loc, p->d_status, out, a);   \
+                           p->d_prog, p->d_lane_seg, p->d_lane_loc, p->d_status,             \
+                           p->d_stats, out, a);                                              \
         break;
         GS_WALK_CASE(1)
         GS_WALK_CASE(2)
