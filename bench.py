@@ -10,7 +10,9 @@ seeded linear-Gaussian DAG (edge probability 0.15, weights +-U[0.3, 1.0]);
 Prints one JSON line.  Besides the contract fields it carries
   roofline      the walk kernel against the HBM write roofline (4 algorithmic
                 bytes per family), timed with HIP events on the launch stream;
-  valu          the walk's algorithmic FP32 flops against the FP32 vector peak;
+  valu          the walk's algorithmic FP32 flops against the FP32 vector peak without
+                packed instructions (78.6 TFLOP/s: the library is built with packed FP32
+                switched off);
   fp64_walk     the same step with the walk in FP64 (families/s);
   fp32_vs_fp64  max relative RSS difference of the two walks over the whole table;
   batched       256 bootstrap datasets (m 12..18, n 200..2000) in one graph replay of
@@ -18,7 +20,11 @@ Prints one JSON line.  Besides the contract fields it carries
                 gs_score_all calls with the same plans;
   adjoint       forward + hand-written backward at m = 14, n = 500 (the loss
                 sum_c logsumexp_S(-BIC));
-  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload.
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload, with the
+                largest difference between those oracle values and the GPU table
+                (measured after the timed region);
+  host          CPU model, host threads, git revision (when the tree has one) and a
+                hash of the library sources.
 """
 from __future__ import annotations
 
@@ -34,7 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_VECTOR_PEAK_TFLOPS = 78.6  # non-packed FP32 (packed FP32 is switched off in the build)
 WORKLOADS = {"c3_m26_n5000": "c3_m26_n5000", "c2_m20_n1000": "c2_m20_n1000",
              "c1_m8_n200": "c1_m8_n200"}
 
@@ -65,19 +71,56 @@ def load_traffic(workload: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(X, m, sample: int, seed: int = 1):
+def cpu_baseline(X, m, sample: int, table, seed: int = 1):
+    """Times the oracle on `sample` random families, then compares those values with
+    the GPU's BIC table (a device tensor) on the same indices."""
     import numpy as np
+    import torch
 
     import oracle
     threads = oracle.default_threads()
+    n = X.shape[0]
     rng = np.random.default_rng(seed)
     idx = rng.choice(m * (1 << (m - 1)), size=sample, replace=False).astype(np.int64)
     t0 = time.perf_counter()
-    oracle.score_indices(X, idx, oracle.OUT_BIC, threads=threads)
+    ref = oracle.score_indices(X, idx, oracle.OUT_BIC, threads=threads)
     dt = time.perf_counter() - t0
+    got = table[torch.as_tensor(idx, device=table.device)].double().cpu().numpy()
+    dbic = float(np.abs(got - ref).max())
     return {"value": sample / dt, "unit": "families/s", "cores": threads, "kind": "oracle",
             "sample": f"{sample} uniformly drawn families of the same table (BIC, FP64 "
-                      f"Householder per family), {dt:.2f} s"}
+                      f"Householder per family), {dt:.2f} s",
+            "gpu_vs_oracle": {"families": sample, "max_abs_bic_err": dbic,
+                              "implied_max_rel_rss_err": math.expm1(dbic / n)}}
+
+
+def host_info() -> dict:
+    import subprocess
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    rev = None
+    try:
+        r = subprocess.run(["git", "-C", ROOT, "rev-parse", "HEAD"], capture_output=True,
+                           text=True, timeout=10)
+        rev = r.stdout.strip() or None if r.returncode == 0 else None
+    except (OSError, subprocess.SubprocessError):
+        pass
+    h = hashlib.sha256()
+    for sub in ("paper_1901_07643_amd/csrc", "include"):
+        d = os.path.join(ROOT, sub)
+        for f in sorted(os.listdir(d)):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "host_threads": threads, "git_rev": rev,
+            "source_sha16": h.hexdigest()[:16]}
 
 
 def _event_ms(fn, steps: int, stream) -> float:
@@ -293,7 +336,9 @@ def main():
                      "traffic": traffic, "kernel": "walk_kernel<float,5,true,4>",
                      "kernel_ms": stage_ms[2]},
         "valu": {"achieved": valu_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                 "frac": valu_tflops / FP32_VECTOR_PEAK_TFLOPS},
+                 "frac": valu_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                 "note": "algorithmic flops (Sec. 5 T(m) + 4 per family) over the walk time, "
+                         "against the non-packed FP32 vector peak"},
         "stages_ms": {"r0_qr": stage_ms[0], "anchors": stage_ms[1], "walk": stage_ms[2],
                       "call": stage_ms[3]},
     }
@@ -337,9 +382,12 @@ def main():
     if not args.no_cpu_baseline:
         print(f"# cpu baseline: oracle on {args.cpu_sample} families ...", file=sys.stderr,
               flush=True)
-        res["cpu_baseline"] = cpu_baseline(X_host, m, args.cpu_sample)
+        gs.score_all(X, plan=plan, what="bic", precision="fp32", out=out)
+        torch.cuda.synchronize()
+        res["cpu_baseline"] = cpu_baseline(X_host, m, args.cpu_sample, out)
     else:
         res["cpu_baseline"] = None
+    res["host"] = host_info()
     print(json.dumps(res), flush=True)
 
 

@@ -105,6 +105,12 @@ int gs_plan_tuned(int m, int k, int ks, gs_plan_t **out);
  * enqueued must have finished. */
 void gs_plan_destroy(gs_plan_t *plan);
 
+/* Device bytes the plan's workspace takes for data of n rows (backward != 0: including
+ * the adjoint's buffers), host integer arithmetic only.  Setting the environment
+ * variable GS_WORKSPACE_LIMIT to a byte count makes every call whose workspace would
+ * exceed it fail with GS_ENOMEM before touching the device. */
+int gs_plan_workspace_bytes(const gs_plan_t *plan, int64_t n, int backward, int64_t *bytes);
+
 /* Sizes chosen by the plan (host struct). */
 int gs_plan_get_info(const gs_plan_t *plan, gs_plan_info_t *info);
 
@@ -128,6 +134,14 @@ int gs_qr_r0(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
  *   what: GS_OUT_BIC or GS_OUT_RSS. */
 int gs_score_all(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
                  float *scores, int what, void *stream);
+
+/* Testing: the FP32 walk of gs_score_all (same plan, same launch, same store path)
+ * with every table write replaced by an atomic increment of a 32-bit counter at the
+ * same index: counts (device, m * 2^(m-1) uint32, 16-byte aligned, zeroed by the
+ * caller) receives +1 per write.  The paper's split (Sec. 6, Alg. 2) covers every
+ * family exactly once, so a correct plan and kernel leave every counter at 1. */
+int gs_count_writes(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
+                    uint32_t *counts, void *stream);
 
 /* Same, with the whole walk in FP64 and an FP64 table (16-byte aligned). */
 int gs_score_all_f64(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,

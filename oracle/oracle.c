@@ -22,6 +22,13 @@
  * X_S, RSS is the squared norm of the transformed x_c below row |S| -- the
  * squared last diagonal entry of R, which is the QRD-to-regression identity of
  * Sec. 2 ([A,B,C] gives [A,B] -> C).
+ *
+ * A second, independent route (or_score_all_gram) solves the normal equations, the
+ * covariance / Cholesky brute force of Table 1: with G = X^T X accumulated in
+ * x87 extended precision, RSS(c, S) is the last pivot of the Cholesky elimination of
+ * the Gram matrix of [X_S | x_c], i.e. the Schur complement G_cc - G_cS G_SS^-1 G_Sc.
+ * It costs O(|S|^3) per family instead of O(n |S|^2), which makes whole tables of
+ * mid-size problems cheap to check.
  */
 #include <math.h>
 #include <pthread.h>
@@ -176,6 +183,108 @@ static int run_parallel(const double *X, int64_t n, int m, int64_t ldx, const in
         if (jobs[t].status) st = jobs[t].status;
     }
     return st;
+}
+
+/* ---- normal-equations route ------------------------------------------------------ */
+
+#define OR_GRAM_MAXW 41
+
+/* RSS of x_child on the columns in mask from the Gram matrix G (m x m, long double):
+ * Cholesky elimination of the Gram matrix of [X_S (ascending labels) | x_c]; the last
+ * pivot, before its square root, is the squared residual. */
+static double rss_gram(const long double *G, int m, int child, uint64_t mask) {
+    int cols[64];
+    int s = 0;
+    for (int v = 0; v < m; ++v)
+        if ((mask >> v) & 1ull) cols[s++] = v;
+    cols[s] = child;
+    const int w = s + 1;
+    long double L[OR_GRAM_MAXW][OR_GRAM_MAXW];
+    for (int j = 0; j < w; ++j) {
+        long double d = G[cols[j] * m + cols[j]];
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        if (j == w - 1) return (double)d;
+        const long double ljj = sqrtl(d);
+        L[j][j] = ljj;
+        for (int i = j + 1; i < w; ++i) {
+            long double a = G[cols[i] * m + cols[j]];
+            for (int k = 0; k < j; ++k) a -= L[i][k] * L[j][k];
+            L[i][j] = a / ljj;
+        }
+    }
+    return NAN; /* not reached: w >= 1 */
+}
+
+typedef struct {
+    const long double *G;
+    int64_t n;
+    int m;
+    const int64_t *idx;
+    int64_t begin, end;
+    double *out;
+    int what;
+    int status;
+} gramjob_t;
+
+static void *run_gram_job(void *p) {
+    gramjob_t *jb = (gramjob_t *)p;
+    for (int64_t t = jb->begin; t < jb->end; ++t) {
+        int64_t id = jb->idx ? jb->idx[t] : t;
+        int c;
+        uint64_t mask;
+        if (or_family_decode(jb->m, id, &c, &mask) != 0) {
+            jb->out[t] = NAN;
+            jb->status = -1;
+            continue;
+        }
+        double rss = rss_gram(jb->G, jb->m, c, mask);
+        jb->out[t] = jb->what == OR_OUT_RSS ? rss : or_bic(rss, jb->n, __builtin_popcountll(mask));
+    }
+    return NULL;
+}
+
+static int run_gram(const double *X, int64_t n, int m, int64_t ldx, const int64_t *idx,
+                    int64_t count, double *out, int what, int nthreads) {
+    if (!X || !out || n < 1 || m < 1 || m > OR_GRAM_MAXW - 1 || ldx < m) return -1;
+    long double *G = (long double *)malloc(sizeof(long double) * (size_t)m * (size_t)m);
+    if (!G) return -3;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            long double acc = 0.0L;
+            for (int64_t r = 0; r < n; ++r)
+                acc += (long double)X[r * ldx + i] * (long double)X[r * ldx + j];
+            G[i * m + j] = acc;
+        }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (count < nthreads) nthreads = count > 0 ? (int)count : 1;
+    pthread_t th[256];
+    gramjob_t jobs[256];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (gramjob_t){G, n, m, idx, count * t / nthreads, count * (t + 1) / nthreads,
+                              out, what, 0};
+        if (nthreads > 1) {
+            if (pthread_create(&th[t], NULL, run_gram_job, &jobs[t]) != 0) {
+                run_gram_job(&jobs[t]);
+                th[t] = 0;
+            }
+        } else {
+            run_gram_job(&jobs[t]);
+        }
+    }
+    int st = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        if (nthreads > 1 && th[t]) pthread_join(th[t], NULL);
+        if (jobs[t].status) st = jobs[t].status;
+    }
+    free(G);
+    return st;
+}
+
+/* Every family by the normal-equations route, table order. */
+int or_score_all_gram(const double *X, int64_t n, int m, int64_t ldx, double *out, int what,
+                      int nthreads) {
+    return run_gram(X, n, m, ldx, NULL, or_num_families(m), out, what, nthreads);
 }
 
 /* Every family, table order.  out has m * 2^(m-1) doubles. */

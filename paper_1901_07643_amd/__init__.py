@@ -23,7 +23,7 @@ from ._abi import (BatchData, GS_EINVAL, GS_ENOTFINITE, GS_ERANGE, GS_ERANK, GS_
                    GS_OUT_BIC, GS_OUT_RSS, GivScoreError, PlanInfo, check, last_error, lib)
 
 __all__ = [
-    "Plan", "Batch", "score_all", "score_backward", "givscore", "GivScore", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
+    "Plan", "Batch", "score_all", "count_writes", "score_backward", "givscore", "GivScore", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
     "GS_OK", "GS_EINVAL", "GS_ERANK", "GS_ENOTFINITE", "GS_ERANGE", "GS_MAX_M", "lib", "last_error",
 ]
 
@@ -70,6 +70,12 @@ class Plan:
         inf = PlanInfo()
         check(lib().gs_plan_get_info(self.handle, ctypes.byref(inf)))
         return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+
+    def workspace_bytes(self, n: int, backward: bool = False) -> int:
+        """Device bytes the plan holds after a call with n rows."""
+        b = ctypes.c_int64()
+        check(lib().gs_plan_workspace_bytes(self.handle, n, 1 if backward else 0, ctypes.byref(b)))
+        return int(b.value)
 
     def count_emissions(self) -> np.ndarray:
         """Host simulation of the walk: how often each table entry would be written."""
@@ -165,6 +171,26 @@ def score_all(X, plan: Plan | None = None, what: str = "bic", precision: str = "
                  ctypes.c_void_p(out.data_ptr()), w, _stream(X.device)))
         if check_status:
             check(plan.status())
+    return out
+
+
+def count_writes(X, plan: Plan | None = None, out=None):
+    """Testing: how often the FP32 walk writes each table entry (int32 device tensor;
+    a correct plan gives all ones).  Same kernels and store path as score_all."""
+    import torch
+    n, m, ldx = _check_X(X, plan.m if plan else None)
+    plan = plan or Plan(m)
+    N = num_families(m)
+    if out is None:
+        out = torch.zeros(N, dtype=torch.int32, device=X.device)
+    elif out.dtype != torch.int32 or out.numel() != N or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor of m*2^(m-1) elements")
+    else:
+        out.zero_()
+    with torch.cuda.device(X.device):
+        check(lib().gs_count_writes(plan.handle, ctypes.c_void_p(X.data_ptr()), n, m, ldx,
+                                    ctypes.c_void_p(out.data_ptr()), _stream(X.device)))
+        check(plan.status())
     return out
 
 

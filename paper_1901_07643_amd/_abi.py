@@ -66,10 +66,12 @@ def lib():
         "gs_plan_tuned": (i32, [i32, i32, i32, pplan]),
         "gs_plan_destroy": (None, [vp]),
         "gs_plan_get_info": (i32, [vp, ctypes.POINTER(PlanInfo)]),
+        "gs_plan_workspace_bytes": (i32, [vp, i64, i32, ctypes.POINTER(i64)]),
         "gs_plan_count_emissions": (i32, [vp, ctypes.POINTER(ctypes.c_int32), i64]),
         "gs_qr_r0": (i32, [vp, vp, i64, i32, i64, vp, vp]),
         "gs_score_all": (i32, [vp, vp, i64, i32, i64, vp, i32, vp]),
         "gs_score_all_f64": (i32, [vp, vp, i64, i32, i64, vp, i32, vp]),
+        "gs_count_writes": (i32, [vp, vp, i64, i32, i64, vp, vp]),
         "gs_score_backward": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
         "gs_score_backward_f64": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
         "gs_sync_status": (i32, [vp]),

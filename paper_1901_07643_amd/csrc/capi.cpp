@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstddef>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -48,7 +49,38 @@ void free_device(gs_plan_s *p) {
     p->device = -1;
 }
 
+// Device bytes a plan holds after a call with n rows (the adjoint's extra buffers
+// with backward != 0).
+int64_t workspace_bytes(const gs_plan_s *p, int64_t n, bool backward) {
+    const int64_t m2 = int64_t(p->m) * p->m;
+    int64_t b = int64_t(p->prog.size()) * 4 + int64_t(p->lane_seg.size()) * 4 +
+                int64_t(p->lane_loc.size()) + m2 * 8 + p->nseg * p->k * 32 * 8 + p->nseg * 32 * 8 +
+                int64_t(sizeof(int)) * 4 + int64_t(sizeof(ColStats)) +
+                2 * qr_workspace_elems(n, p->m) * 8;
+    if (backward)
+        b += p->nseg * p->k * 32 * 8 + p->nseg * 32 * 8 + p->nseg * m2 * 8 +
+             adjoint_partial_chunks(p->nseg) * m2 * 8 + 2 * m2 * 8;
+    return b;
+}
+
+// A cap on the workspace from the environment (GS_WORKSPACE_LIMIT, bytes), checked
+// before any device call: a host-forced GS_ENOMEM for callers and tests.
+int check_workspace_cap(const gs_plan_s *p, int64_t n, bool backward) {
+    const char *env = std::getenv("GS_WORKSPACE_LIMIT");
+    if (!env || !*env) return GS_OK;
+    char *end = nullptr;
+    const long long cap = std::strtoll(env, &end, 10);
+    if (end == env || cap < 0) return fail(GS_EINVAL, "GS_WORKSPACE_LIMIT is not a byte count");
+    const int64_t need = workspace_bytes(p, n, backward);
+    if (need > cap)
+        return fail(GS_ENOMEM, "workspace of " + std::to_string(need) +
+                                   " bytes exceeds GS_WORKSPACE_LIMIT=" + std::to_string(cap));
+    return GS_OK;
+}
+
 int ensure_workspace(gs_plan_s *p, int64_t n) {
+    int st = check_workspace_cap(p, n, false);
+    if (st != GS_OK) return st;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -168,8 +200,10 @@ int score_all_impl(gs_plan_s *p, const double *X, int64_t n, int m, int64_t ldx,
     return GS_OK;
 }
 
-int ensure_adjoint_workspace(gs_plan_s *p) {
+int ensure_adjoint_workspace(gs_plan_s *p, int64_t n) {
     if (p->d_anchorbar) return GS_OK;
+    int st = check_workspace_cap(p, n, true);
+    if (st != GS_OK) return st;
     const size_t m2 = size_t(p->m) * p->m;
     const size_t nch = size_t(adjoint_partial_chunks(p->nseg));
     hipError_t e;
@@ -201,8 +235,9 @@ int score_backward_impl(gs_plan_s *p, const double *X, int64_t n, int m, int64_t
     if (lddx < m) return fail(GS_EINVAL, std::string(who) + ": lddx < m");
     if (what != GS_OUT_BIC && what != GS_OUT_RSS)
         return fail(GS_EINVAL, std::string(who) + ": what must be GS_OUT_BIC or GS_OUT_RSS");
+    if ((st = check_workspace_cap(p, n, true)) != GS_OK) return st;
     if ((st = ensure_workspace(p, n)) != GS_OK) return st;
-    if ((st = ensure_adjoint_workspace(p)) != GS_OK) return st;
+    if ((st = ensure_adjoint_workspace(p, n)) != GS_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if ((st = front_half<T>(p, X, n, m, ldx, s, nullptr)) != GS_OK) return st;
     hipError_t e = launch_walk_adjoint<T>(p, static_cast<const T *>(p->d_anchor),
@@ -268,9 +303,31 @@ int gs_score_all(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx, f
     return score_all_impl<float>(p, X, n, m, ldx, scores, what, stream, "gs_score_all");
 }
 
+int gs_count_writes(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx,
+                    uint32_t *counts, void *stream) {
+    int st = check_common(p, X, n, m, ldx, counts, "gs_count_writes");
+    if (st != GS_OK) return st;
+    if ((st = ensure_workspace(p, n)) != GS_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if ((st = front_half<float>(p, X, n, m, ldx, s, nullptr)) != GS_OK) return st;
+    hipError_t e = launch_walk_count(p, static_cast<const float *>(p->d_anchor),
+                                     static_cast<const float *>(p->d_tail), counts, n, s);
+    if (e != hipSuccess) return hip_fail(e, "walk launch");
+    if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    p->last_stream = s;
+    return GS_OK;
+}
+
 int gs_score_all_f64(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx, double *scores,
                      int what, void *stream) {
     return score_all_impl<double>(p, X, n, m, ldx, scores, what, stream, "gs_score_all_f64");
+}
+
+int gs_plan_workspace_bytes(const gs_plan_t *p, int64_t n, int backward, int64_t *bytes) {
+    if (!p || !bytes) return fail(GS_EINVAL, "gs_plan_workspace_bytes: NULL argument");
+    if (n <= p->m) return fail(GS_EINVAL, "gs_plan_workspace_bytes: need n > m");
+    *bytes = workspace_bytes(p, n, backward != 0);
+    return GS_OK;
 }
 
 int gs_sync_status(gs_plan_t *p) {

@@ -74,6 +74,7 @@ struct gs_plan_s {
 
 namespace gs {
 
+#ifdef __HIPCC__
 // Order the LDS accesses of one wave: some lanes write, others read.  Without the
 // fences the compiler may treat the cross-lane exchange as a data race and move
 // the reads ahead of the writes.
@@ -99,6 +100,7 @@ __device__ __forceinline__ double rcp_newton(double d) {
     return r;
 }
 constexpr double GS_DBL_MIN = 2.2250738585072014e-308;
+#endif  // __HIPCC__: the host-only planner build sees none of the device helpers
 
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
@@ -168,6 +170,9 @@ hipError_t launch_walk_f32(const gs_plan_s *p, const float *anchor, const float 
                            int64_t n, bool bic, hipStream_t s);
 hipError_t launch_walk_f64(const gs_plan_s *p, const double *anchor, const double *tail,
                            double *out, int64_t n, bool bic, hipStream_t s);
+// The FP32 walk with every table write replaced by an atomic +1 of a uint32 counter.
+hipError_t launch_walk_count(const gs_plan_s *p, const float *anchor, const float *tail,
+                             uint32_t *counts, int64_t n, hipStream_t s);
 
 // Batched launches (one per stage for every dataset of a batch)
 hipError_t launch_walk_batched_f32(const BatchItem *items, const int32_t *wave_item,

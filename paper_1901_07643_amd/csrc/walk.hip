@@ -260,13 +260,30 @@ __device__ __forceinline__ void global_store16(uint64_t dst, const float4 &v) {
     *reinterpret_cast<global_float4 *>(dst) = w;
 }
 
+// Write-count mode of the walk (testing): every 4-byte table entry a store would write
+// gets an atomic +1 instead, at the same address, through the same store path.
+__device__ __forceinline__ void count16(uint64_t dst) {
+    unsigned *p = reinterpret_cast<unsigned *>(dst);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) atomicAdd(p + i, 1u);
+}
+template <int CNT, typename T>
+__device__ __forceinline__ void count_line(T *dst) {
+    static_assert(sizeof(T) == 4, "write counts are taken on the FP32 table layout");
+    unsigned *p = reinterpret_cast<unsigned *>(dst);
+#pragma unroll
+    for (int i = 0; i < CNT; ++i) atomicAdd(p + i, 1u);
+}
+
+enum WalkMode { WALK_STORE = 0, WALK_COUNT = 1 };
+
 constexpr int WALK_WAVES = 4;  // waves per workgroup
 #ifndef WALK_MIN_WAVES
 #define WALK_MIN_WAVES 5
 #endif
 
 // The walk of one wave (wave index wid of its dataset's packed wave table).
-template <typename T, int KS, bool BIC>
+template <typename T, int KS, bool BIC, int MODE>
 __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T *__restrict__ tail,
                                           const uint32_t *__restrict__ prog,
                                           const int32_t *__restrict__ lane_seg,
@@ -506,15 +523,21 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
             });
             static_for<0, 8>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
-                if (ch < int(dd[t] & 15u)) global_store16((dd[t] & ~uint64_t(15)) + uint64_t(ch) * 16, vv[t]);
+                if (ch < int(dd[t] & 15u)) {
+                    const uint64_t dst = (dd[t] & ~uint64_t(15)) + uint64_t(ch) * 16;
+                    if constexpr (MODE == WALK_COUNT) count16(dst);
+                    else global_store16(dst, vv[t]);
+                }
             });
         } else {
             if (cls == 1) {
                 T h[NH];
                 static_for<0, NH>([&](auto ic) { h[decltype(ic)::value] = inner_entry(ic); });
-                store_line<NH>(out + cbase + int64_t(Shi >> 1), h);
+                if constexpr (MODE == WALK_COUNT) count_line<NH>(out + cbase + int64_t(Shi >> 1));
+                else store_line<NH>(out + cbase + int64_t(Shi >> 1), h);
             } else if (child) {
-                store_line<NS>(out + cbase + int64_t(low | high), o);
+                if constexpr (MODE == WALK_COUNT) count_line<NS>(out + cbase + int64_t(low | high));
+                else store_line<NS>(out + cbase + int64_t(low | high), o);
             }
         }
     };
@@ -545,7 +568,7 @@ __host__ __device__ constexpr size_t walk_wave_lds(int q) {
     return walk_stage_bytes<T, KS>() + size_t(q > 0 ? q : 1) * 64 * sizeof(T);
 }
 
-template <typename T, int KS, bool BIC, int MINW>
+template <typename T, int KS, bool BIC, int MINW, int MODE = WALK_STORE>
 __global__ __launch_bounds__(64 * WALK_WAVES) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void walk_kernel(const T *__restrict__ anchor, const T *__restrict__ tail,
                  const uint32_t *__restrict__ prog, const int32_t *__restrict__ lane_seg,
@@ -559,7 +582,7 @@ void walk_kernel(const T *__restrict__ anchor, const T *__restrict__ tail,
     constexpr size_t stage = walk_stage_bytes<T, KS>();
     float4 *Sg = reinterpret_cast<float4 *>(base);
     uint64_t *Dg = reinterpret_cast<uint64_t *>(base + STAGE_LINES * STAGE_CHUNKS * 16);
-    walk_body<T, KS, BIC>(anchor, tail, prog, lane_seg, lane_loc, status, stats, out, a, wid,
+    walk_body<T, KS, BIC, MODE>(anchor, tail, prog, lane_seg, lane_loc, status, stats, out, a, wid,
                           reinterpret_cast<T(*)[64]>(base + stage), Sg, Dg);
 }
 
@@ -589,7 +612,8 @@ void walk_batched_kernel(const BatchItem *__restrict__ items, const int32_t *__r
     a.nlog = d.nlog;
     a.lnn = d.lnn;
     a.nln2 = d.nln2;
-    walk_body<T, KS, BIC>(static_cast<const T *>(d.anchor), static_cast<const T *>(d.tail), d.prog,
+    walk_body<T, KS, BIC, WALK_STORE>(static_cast<const T *>(d.anchor),
+                                      static_cast<const T *>(d.tail), d.prog,
                           d.lane_seg, d.lane_loc, d.status, d.stats, static_cast<T *>(d.out), a,
                           wave_local[gw], reinterpret_cast<T(*)[64]>(base + stage), Sg, Dg);
 }
@@ -600,7 +624,7 @@ void walk_batched_kernel(const BatchItem *__restrict__ items, const int32_t *__r
 template <typename T, int KS>
 constexpr int kMinWaves = !std::is_same_v<T, float> ? 1 : (KS == 5 ? 4 : (KS < 5 ? WALK_MIN_WAVES : 1));
 
-template <typename T, bool BIC>
+template <typename T, bool BIC, int MODE = WALK_STORE>
 static hipError_t launch_walk_t(const gs_plan_s *p, const T *anchor, const T *tail, T *out,
                                 int64_t n, hipStream_t s) {
     WalkArgs a;
@@ -621,7 +645,8 @@ static hipError_t launch_walk_t(const gs_plan_s *p, const T *anchor, const T *ta
     switch (p->ks) {
 #define GS_WALK_CASE(KSV)                                                                   \
     case KSV:                                                                               \
-        hipLaunchKernelGGL((walk_kernel<T, KSV, BIC, kMinWaves<T, KSV>>), grid, block, lds, s, \
+        hipLaunchKernelGGL((walk_kernel<T, KSV, BIC, kMinWaves<T, KSV>, MODE>), grid, block, lds, \
+                           s,                                                                  \
                            anchor, tail,                                                    \
                            p->d_prog, p->d_lane_seg, p->d_lane_loc, p->d_status,             \
                            p->d_stats, out, a);                                              \
@@ -656,6 +681,12 @@ hipError_t launch_walk_f32(const gs_plan_s *p, const float *anchor, const float 
                            int64_t n, bool bic, hipStream_t s) {
     return bic ? launch_walk_t<float, true>(p, anchor, tail, out, n, s)
                : launch_walk_t<float, false>(p, anchor, tail, out, n, s);
+}
+
+hipError_t launch_walk_count(const gs_plan_s *p, const float *anchor, const float *tail,
+                             uint32_t *counts, int64_t n, hipStream_t s) {
+    return launch_walk_t<float, true, WALK_COUNT>(p, anchor, tail, reinterpret_cast<float *>(counts),
+                                                  n, s);
 }
 
 hipError_t launch_walk_f64(const gs_plan_s *p, const double *anchor, const double *tail,

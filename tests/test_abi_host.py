@@ -150,3 +150,26 @@ def test_batch_argument_errors(gs):
     assert L.gs_score_batched(None, d, 0, 0, None) == gs.GS_EINVAL
     del fake
     b.close()
+
+
+def test_workspace_cap_forces_enomem_before_the_device(gs, monkeypatch):
+    """GS_WORKSPACE_LIMIT below the plan's workspace: gs_score_all and gs_score_backward
+    fail with GS_ENOMEM during argument processing, before any device call (the data
+    pointers here are never dereferenced)."""
+    m, n = 12, 300
+    p = gs.Plan(m)
+    need = p.workspace_bytes(n)
+    need_bw = p.workspace_bytes(n, backward=True)
+    assert 0 < need < need_bw
+    info = p.info
+    # anchors of every segment (FP64 slots), their tails, two TSQR buffers: a lower bound
+    assert need >= info["num_segments"] * (info["k"] + 1) * 32 * 8 + 2 * ((n + 127) // 128) * m * m * 8
+    fake = ctypes.c_void_p(0x100000)
+    L = gs.lib()
+    monkeypatch.setenv("GS_WORKSPACE_LIMIT", str(need - 1))
+    assert L.gs_score_all(p.handle, fake, n, m, m, fake, gs.GS_OK, None) == gs._abi.GS_ENOMEM
+    assert "GS_WORKSPACE_LIMIT" in gs.last_error()
+    monkeypatch.setenv("GS_WORKSPACE_LIMIT", str(need_bw - 1))
+    assert L.gs_score_backward(p.handle, fake, n, m, m, fake, 0, fake, m, None) == gs._abi.GS_ENOMEM
+    monkeypatch.setenv("GS_WORKSPACE_LIMIT", "not-a-number")
+    assert L.gs_score_all(p.handle, fake, n, m, m, fake, 0, None) == gs.GS_EINVAL

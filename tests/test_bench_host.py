@@ -27,3 +27,9 @@ def test_runtime_T_is_the_walks_swap_cost(m):
     seq = gs.upsilon(m)
     assert len(seq) == 2 ** m - m - 1
     assert bench.runtime_T(m) == sum(6 * (m - i + 1) for i in seq)
+
+
+def test_host_info_fields():
+    h = bench.host_info()
+    assert set(h) == {"cpu_model", "host_threads", "git_rev", "source_sha16"}
+    assert h["host_threads"] >= 1 and len(h["source_sha16"]) == 16

@@ -122,6 +122,24 @@ def test_full_size_sampled(gs, name):
         torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_c2_whole_table(gs, prec):
+    """m = 20, n = 1000: all 10,485,760 families of both walks, RSS and BIC, against the
+    oracle's normal-equations route (pinned to its per-family Householder route on
+    whole tables and to exact rational Gram determinant ratios)."""
+    c = CONFIGS["c2_m20_n1000"]
+    X = config_data("c2_m20_n1000")
+    print(f"\nC2 whole table, {prec}", flush=True)
+    ref_rss = oracle.score_all_gram(X, oracle.OUT_RSS)
+    ref_bic = oracle.score_all_gram(X, oracle.OUT_BIC)
+    got = _run(gs, X, "rss", prec).cpu().numpy()
+    err = _assert_rss(got, ref_rss, TOL[prec], f"C2 rss {prec}")
+    got = _run(gs, X, "bic", prec).cpu().numpy()
+    _assert_bic(got, ref_bic, c.n, prec, f"C2 bic {prec}")
+    print(f"C2 whole table {prec}: max rel RSS err {err:.3e}, "
+          f"max |dBIC| {np.abs(got - ref_bic).max():.3e}")
+
+
 @pytest.mark.parametrize("name", ["c2_m20_n1000", "c3_m26_n5000"])
 def test_fp32_walk_vs_fp64_walk_whole_table(gs, name):
     """Every entry of the FP32 walk against the FP64 walk of the same plan (the FP64
@@ -382,3 +400,42 @@ def test_fp32_precision_envelope(gs, delta):
         assert err <= env
         if env <= TOL["fp32"]:
             assert err <= TOL["fp32"]
+
+
+# ---------------------------------------------------------------- exactly once, on the device
+
+@pytest.mark.parametrize("name,k,ks", [("c3_m26_n5000", 0, 0), ("c2_m20_n1000", 0, 0),
+                                       ("c2_m20_n1000", 13, 5), ("c2_m20_n1000", 9, 3),
+                                       ("c5_m14_n500", 14, 6), ("c1_m8_n200", 4, 2)])
+def test_device_writes_exactly_once(gs, name, k, ks):
+    """The walk's own store path with each write turned into an atomic +1 (gs_count_writes):
+    every table entry must be written exactly once -- the split of Sec. 6 covers every
+    family once -- at the default m = 26 plan the benchmark times, and at plans with
+    other segment and inner-block sizes (lane-owned stores for inner blocks other than 5)."""
+    X = config_data(name)
+    m = X.shape[1]
+    plan = gs.Plan(m, k, ks)
+    print(f"\n{name} k={plan.info['k']} ks={plan.info['ks']}", flush=True)
+    cnt = gs.count_writes(torch.as_tensor(X, device="cuda"), plan=plan)
+    ones = int((cnt == 1).sum().item())
+    assert ones == cnt.numel(), (f"{cnt.numel() - ones} entries not written exactly once "
+                                 f"(min {cnt.min().item()}, max {cnt.max().item()})")
+    del cnt
+    torch.cuda.empty_cache()
+
+
+def test_workspace_cap(gs, monkeypatch):
+    """GS_WORKSPACE_LIMIT one byte below the plan's workspace gives GS_ENOMEM on a fresh
+    plan; at the limit the call succeeds and matches the oracle."""
+    X = config_data("c1_m8_n200")
+    n, m = X.shape
+    Xd = torch.as_tensor(X, device="cuda")
+    plan = gs.Plan(m)
+    need = plan.workspace_bytes(n)
+    monkeypatch.setenv("GS_WORKSPACE_LIMIT", str(need - 1))
+    with pytest.raises(gs.GivScoreError) as e:
+        gs.score_all(Xd, plan=plan, what="rss", precision="fp64")
+    assert e.value.code == gs._abi.GS_ENOMEM
+    monkeypatch.setenv("GS_WORKSPACE_LIMIT", str(need))
+    got = gs.score_all(Xd, plan=plan, what="rss", precision="fp64").cpu().numpy()
+    _assert_rss(got, oracle.score_all(X, oracle.OUT_RSS), TOL["fp64"], "capped workspace")

@@ -63,3 +63,34 @@ def test_gradient_of_single_family_is_residual_outer_product():
     w[S] = -beta
     r = X @ w
     assert np.allclose(dX, 2 * np.outer(r, w), atol=1e-10)
+
+
+@pytest.mark.slow
+def test_c5_gradient_vs_central_fd_all_columns():
+    """The differentiation workload itself (m = 14, n = 500): the closed form against
+    central differences, h = 1e-3 in FP64, on 70 seeded entries of X, five in each of
+    the 14 columns.  The loss is evaluated on the oracle's normal-equations route
+    (pinned to the Householder route in test_oracle_pins.py), which keeps the 140 loss
+    evaluations cheap."""
+    from datagen import config_data
+    X = config_data("c5_m14_n500")
+    n, m = X.shape
+    L, dX, _, _ = oracle.loss_and_grad(X)
+
+    def loss(Y):
+        return oracle.logsumexp_loss(oracle.score_all_gram(Y, oracle.OUT_BIC), m)[0]
+
+    assert abs(loss(X) - L) <= 1e-9 * abs(L)
+    rng = np.random.default_rng(14)
+    h = 1e-3
+    worst = 0.0
+    for j in range(m):
+        for i in rng.choice(n, size=5, replace=False):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[i, j] += h
+            Xm[i, j] -= h
+            fd = (loss(Xp) - loss(Xm)) / (2 * h)
+            err = abs(fd - dX[i, j]) / max(1.0, abs(dX[i, j]))
+            worst = max(worst, err)
+            assert err <= 1e-5, (i, j, fd, dX[i, j])
+    print(f"\nC5 central differences, 70 entries: max error {worst:.3e}")

@@ -174,3 +174,50 @@ def test_oracle_threads_agree():
     assert np.array_equal(a, b)
     idx = np.array([5, 17, 0, 2303, 1000])
     assert np.array_equal(oracle.score_indices(X, idx, oracle.OUT_RSS, threads=3), a[idx])
+
+
+# ---- the normal-equations route (or_score_all_gram): the same pins, plus agreement
+# with the Householder route on whole tables
+
+def test_gram_route_exact_determinant_ratio():
+    rng = np.random.default_rng(12)
+    n, m = 9, 5
+    Xi = rng.integers(-6, 7, size=(n, m))
+    X = Xi.astype(np.float64)
+    G = [[Fraction(int(v)) for v in row] for row in (Xi.T @ Xi)]
+    T = oracle.score_all_gram(X, oracle.OUT_RSS, threads=2)
+    for c, S in _families(m):
+        idx = list(S) + [c]
+        num = _det_fraction([[G[a][b] for b in idx] for a in idx])
+        den = _det_fraction([[G[a][b] for b in S] for a in S]) if S else Fraction(1)
+        exact = float(num / den)
+        got = T[oracle.family_index(m, c, _mask(S))]
+        assert abs(got - exact) <= 1e-12 * max(1.0, abs(exact)), (c, S, got, exact)
+
+
+def test_gram_route_matches_lstsq_and_closed_forms():
+    m, n = 6, 40
+    X = linear_gaussian(m, n, 0.4, 0.5, 1.5, seed=106)
+    T = oracle.score_all_gram(X, oracle.OUT_RSS, threads=2)
+    Ginv = np.linalg.inv(X.T @ X)
+    full = (1 << m) - 1
+    for c, S in _families(m):
+        y = X[:, c]
+        r = y - X[:, list(S)] @ np.linalg.lstsq(X[:, list(S)], y, rcond=None)[0] if S else y
+        assert T[oracle.family_index(m, c, _mask(S))] == pytest.approx(float(r @ r), rel=1e-11)
+    for c in range(m):
+        assert T[oracle.family_index(m, c, 0)] == pytest.approx(X[:, c] @ X[:, c], rel=1e-13)
+        assert T[oracle.family_index(m, c, full & ~(1 << c))] == pytest.approx(1 / Ginv[c, c],
+                                                                               rel=1e-10)
+
+
+@pytest.mark.parametrize("m,n,seed", [(8, 200, 8), (10, 11, 5), (12, 300, 3)])
+def test_gram_route_agrees_with_householder(m, n, seed):
+    X = linear_gaussian(m, n, 0.3, 0.5, 1.5, seed=seed)
+    for what in (oracle.OUT_RSS, oracle.OUT_BIC):
+        a = oracle.score_all(X, what, threads=4)
+        b = oracle.score_all_gram(X, what, threads=3)
+        if what == oracle.OUT_RSS:
+            assert np.max(np.abs(a - b) / a) <= 1e-12
+        else:
+            assert np.max(np.abs(a - b)) <= 1e-9
