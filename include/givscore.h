@@ -135,6 +135,26 @@ int gs_qr_r0(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
 int gs_score_all(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
                  float *scores, int what, void *stream);
 
+/* gs_score_all without allocation, for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and results as gs_score_all (bit for bit), but every piece
+ * of workspace lives in a file-scope device array of GS_STATIC_SCRATCH_BYTES
+ * (32 MiB), which each device that runs this call holds until the process ends; no
+ * allocation of any kind happens in the call.  The plan's walk program and lane
+ * tables are copied into that array (hipMemcpyAsync from the plan's host memory on
+ * `stream`) when the previous call on the device used another plan.
+ *   status_code: device int (or NULL); receives the gs_status of the data (GS_OK,
+ *     GS_ERANK, GS_ENOTFINITE, GS_ERANGE) when the stream reaches the end of the call
+ *     (the plan's gs_sync_status does not see this path).
+ * Returns GS_ENOMEM, before any device work, when the plan and n need more than the
+ * array holds (m = 26 with the default plan needs about 16 MB at n = 5000; m >= 28
+ * does not fit).  All calls on one device share the array and it keeps the last
+ * call's contents: calls that overlap on a device race and must be serialised by the
+ * caller. */
+#define GS_STATIC_SCRATCH_BYTES (32u << 20)
+int gs_score_all_static(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
+                        float *scores, int what, int *status_code, void *stream);
+
 /* Testing: the FP32 walk of gs_score_all (same plan, same launch, same store path)
  * with every table write replaced by an atomic increment of a 32-bit counter at the
  * same index: counts (device, m * 2^(m-1) uint32, 16-byte aligned, zeroed by the

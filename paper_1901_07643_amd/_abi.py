@@ -72,6 +72,7 @@ def lib():
         "gs_score_all": (i32, [vp, vp, i64, i32, i64, vp, i32, vp]),
         "gs_score_all_f64": (i32, [vp, vp, i64, i32, i64, vp, i32, vp]),
         "gs_count_writes": (i32, [vp, vp, i64, i32, i64, vp, vp]),
+        "gs_score_all_static": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, vp]),
         "gs_score_backward": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
         "gs_score_backward_f64": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
         "gs_sync_status": (i32, [vp]),

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build", "givscore")
 LIB = os.path.join(HERE, "libgivscore.so")
-SOURCES = ["plan.cpp", "capi.cpp", "batch.cpp", "qr.hip", "anchor.hip", "walk.hip", "adjoint.hip"]
+SOURCES = ["plan.cpp", "capi.cpp", "batch.cpp", "qr.hip", "anchor.hip", "walk.hip", "adjoint.hip",
+           "static_ws.hip"]
 ARCH = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are switched off for all device code.

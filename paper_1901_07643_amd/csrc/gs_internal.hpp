@@ -35,7 +35,9 @@ struct ColStats {
 // others) makes the walks take the guarded Givens steps.
 constexpr double GS_GUARD_VIF = 1e8;
 
+
 struct gs_plan_s {
+    uint64_t id = 0;  // unique per plan created in this process
     int m = 0, k = 0, ks = 0, q = 0;
     int64_t nseg = 0, nsub = 0;
     std::vector<uint32_t> prog;  // 2 words per sub-walk (layout in walk_program.hpp)
@@ -165,7 +167,20 @@ template <typename T>
 hipError_t launch_anchors(const double *R0, const ColStats *stats, int m, int k, int ks,
                           int64_t nseg, T *anchor, T *tail, hipStream_t s);
 
+// Device tables a walk launch reads besides its anchors: the plan's program and packed
+// lane tables, the dataset's status word and column statistics.
+struct WalkTables {
+    const uint32_t *prog;
+    const int32_t *lane_seg;
+    const int8_t *lane_loc;
+    int *status;
+    const ColStats *stats;
+};
+
 // The walk.  T = float or double; writes the full table.
+hipError_t launch_walk_f32_tables(const gs_plan_s *p, const WalkTables &t, const float *anchor,
+                                  const float *tail, float *out, int64_t n, bool bic,
+                                  hipStream_t s);
 hipError_t launch_walk_f32(const gs_plan_s *p, const float *anchor, const float *tail, float *out,
                            int64_t n, bool bic, hipStream_t s);
 hipError_t launch_walk_f64(const gs_plan_s *p, const double *anchor, const double *tail,

@@ -17,6 +17,7 @@
 // steps is (2^q - 1) ks + (2^q - q - 1) + 2^q (2^ks - ks - 1) = 2^k - k - 1, the
 // optimum of Sec. 4, and every table line of 2^ks consecutive entries is produced
 // by one inner walk.
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -328,6 +329,8 @@ int gs_plan_tuned(int m, int k, int ks, gs_plan_t **out) {
         return fail(GS_EINVAL, "gs_plan: need ks <= k <= m and k - ks <= 16");
     gs_plan_s *p = new (std::nothrow) gs_plan_s();
     if (!p) return fail(GS_ENOMEM, "gs_plan: host allocation failed");
+    static std::atomic<uint64_t> next_id{1};
+    p->id = next_id.fetch_add(1);
     p->m = m;
     p->k = k;
     p->ks = ks;

@@ -625,8 +625,8 @@ template <typename T, int KS>
 constexpr int kMinWaves = !std::is_same_v<T, float> ? 1 : (KS == 5 ? 4 : (KS < 5 ? WALK_MIN_WAVES : 1));
 
 template <typename T, bool BIC, int MODE = WALK_STORE>
-static hipError_t launch_walk_t(const gs_plan_s *p, const T *anchor, const T *tail, T *out,
-                                int64_t n, hipStream_t s) {
+static hipError_t launch_walk_t(const gs_plan_s *p, const WalkTables &t, const T *anchor,
+                                const T *tail, T *out, int64_t n, hipStream_t s) {
     WalkArgs a;
     a.m = p->m;
     a.k = p->k;
@@ -648,8 +648,7 @@ static hipError_t launch_walk_t(const gs_plan_s *p, const T *anchor, const T *ta
         hipLaunchKernelGGL((walk_kernel<T, KSV, BIC, kMinWaves<T, KSV>, MODE>), grid, block, lds, \
                            s,                                                                  \
                            anchor, tail,                                                    \
-                           p->d_prog, p->d_lane_seg, p->d_lane_loc, p->d_status,             \
-                           p->d_stats, out, a);                                              \
+                           t.prog, t.lane_seg, t.lane_loc, t.status, t.stats, out, a);      \
         break;
         GS_WALK_CASE(1)
         GS_WALK_CASE(2)
@@ -677,22 +676,32 @@ hipError_t launch_walk_batched_f32(const BatchItem *items, const int32_t *wave_i
     return hipGetLastError();
 }
 
+static WalkTables plan_tables(const gs_plan_s *p) {
+    return WalkTables{p->d_prog, p->d_lane_seg, p->d_lane_loc, p->d_status, p->d_stats};
+}
+
+hipError_t launch_walk_f32_tables(const gs_plan_s *p, const WalkTables &t, const float *anchor,
+                                  const float *tail, float *out, int64_t n, bool bic,
+                                  hipStream_t s) {
+    return bic ? launch_walk_t<float, true>(p, t, anchor, tail, out, n, s)
+               : launch_walk_t<float, false>(p, t, anchor, tail, out, n, s);
+}
+
 hipError_t launch_walk_f32(const gs_plan_s *p, const float *anchor, const float *tail, float *out,
                            int64_t n, bool bic, hipStream_t s) {
-    return bic ? launch_walk_t<float, true>(p, anchor, tail, out, n, s)
-               : launch_walk_t<float, false>(p, anchor, tail, out, n, s);
+    return launch_walk_f32_tables(p, plan_tables(p), anchor, tail, out, n, bic, s);
 }
 
 hipError_t launch_walk_count(const gs_plan_s *p, const float *anchor, const float *tail,
                              uint32_t *counts, int64_t n, hipStream_t s) {
-    return launch_walk_t<float, true, WALK_COUNT>(p, anchor, tail, reinterpret_cast<float *>(counts),
-                                                  n, s);
+    return launch_walk_t<float, true, WALK_COUNT>(p, plan_tables(p), anchor, tail,
+                                                  reinterpret_cast<float *>(counts), n, s);
 }
 
 hipError_t launch_walk_f64(const gs_plan_s *p, const double *anchor, const double *tail,
                            double *out, int64_t n, bool bic, hipStream_t s) {
-    return bic ? launch_walk_t<double, true>(p, anchor, tail, out, n, s)
-               : launch_walk_t<double, false>(p, anchor, tail, out, n, s);
+    return bic ? launch_walk_t<double, true>(p, plan_tables(p), anchor, tail, out, n, s)
+               : launch_walk_t<double, false>(p, plan_tables(p), anchor, tail, out, n, s);
 }
 
 }  // namespace gs
