@@ -195,6 +195,28 @@ def bench_batched(steps: int, stream):
             "walk_waves_per_simd": 4}
 
 
+def bench_reduce(X, plan, steps: int, stream):
+    """The fused consumer gs_score_reduce on the same workload: per child the minimum BIC
+    and its parent set and ln sum exp(-BIC) (and the 8 best parent sets), with no table
+    written.  One step = R0, anchors, the reducing walk and the per-child merge."""
+    import paper_1901_07643_amd as gs
+    nfam = gs.num_families(plan.m)
+    res = {}
+    for top in (0, 8):
+        gs.score_reduce(X, plan=plan, top_k=top)
+        plan.set_timing(True)
+        ms = _event_ms(lambda: gs.score_reduce(X, plan=plan, top_k=top, check_status=False),
+                       steps, stream)
+        stage, _ = plan.timing()
+        plan.set_timing(False)
+        res[f"top{top}"] = {"value": nfam / (ms * 1e-3), "unit": "families/s",
+                            "ms_per_step": ms, "walk_and_merge_ms": stage[2],
+                            "r0_qr_ms": stage[0], "anchors_ms": stage[1]}
+    res["note"] = ("no table written; the walk then does the Givens steps, the BIC scores "
+                   "and the per-lane folds only")
+    return res
+
+
 def bench_adjoint(steps: int, stream):
     """Forward and backward of the loss sum_c logsumexp_S(-BIC) at m = 14, n = 500 (its
     parity against the oracle's closed-form gradient is a GPU test)."""
@@ -244,6 +266,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-walk comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
+    ap.add_argument("--no-reduce", action="store_true", help="skip the fused reduction")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (counter calibration)")
     args = ap.parse_args()
@@ -369,6 +392,11 @@ def main():
         print(f"# fp64 walk {ms64:.4f} ms/step; max rel RSS fp32 vs fp64 {worst:.3e}",
               file=sys.stderr, flush=True)
 
+    if not args.no_reduce:
+        res["fused_reduce"] = bench_reduce(X, plan, args.steps, stream)
+        print(f"# fused reduce: {res['fused_reduce']['top0']['ms_per_step']:.4f} ms/step "
+              f"(top-8 {res['fused_reduce']['top8']['ms_per_step']:.4f})", file=sys.stderr,
+              flush=True)
     if not args.no_batched:
         res["batched"] = bench_batched(args.steps, stream)
         print(f"# batched: {res['batched']['ms_per_step']:.3f} ms/step graph, "

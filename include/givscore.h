@@ -135,6 +135,36 @@ int gs_qr_r0(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
 int gs_score_all(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
                  float *scores, int what, void *stream);
 
+/* Fused consumer of the scores: score-based learning uses the local scores of all
+ * families (Sec. 1), most often as the best parent set per child, a short list of the
+ * best ones, or a soft minimum over all of them.  gs_score_reduce runs the FP32 BIC
+ * walk of gs_score_all but folds every value into per-child results on chip instead of
+ * writing the m 2^(m-1) table (the paper keeps O(m^2) working storage, Sec. 7; here a
+ * few floats per child and segment).  Per child c (arrays of m, device memory):
+ *   best_score[c]    min over parent sets S of BIC(c, S);
+ *   best_parents[c]  a parent mask S reaching it (bit v = variable v; the smallest mask
+ *                    among equal values);
+ *   logsumexp[c]     ln sum over S of exp(-BIC(c, S)), accumulated relative to the
+ *                    minimum (double);
+ *   top_score[c * top_k + j], top_parents[...]: the top_k (0..8) smallest BIC values of
+ *                    child c, ascending, with their parent masks (may be NULL if
+ *                    top_k = 0).
+ * BIC values are those gs_score_all writes (same kernels, same arithmetic).  The merge
+ * over segments runs in a fixed order: the results are reproducible bit for bit.
+ * Workspace: about m 2^(m-k) x 76 bytes beyond gs_score_all's, allocated on the first
+ * call. */
+#define GS_REDUCE_MAX_TOPK 8
+typedef struct {
+    float *best_score;
+    uint32_t *best_parents;
+    double *logsumexp;
+    float *top_score;
+    uint32_t *top_parents;
+    int top_k;
+} gs_reduce_t;
+int gs_score_reduce(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
+                    const gs_reduce_t *out, void *stream);
+
 /* gs_score_all without allocation, for callers that cannot allocate device memory
  * (code under graph capture, tight serving loops, harnesses that forbid hipMalloc).
  * Same arguments, kernels and results as gs_score_all (bit for bit), but every piece

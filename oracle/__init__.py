@@ -169,3 +169,26 @@ def loss_and_grad(X, threads: int | None = None):
     gbar = dbic * (n / rss_t)
     dX, _ = grad_from_gbar(X, gbar, threads)
     return L, dX, dbic, rss_t
+
+
+def reduce_table(table: np.ndarray, m: int, top_k: int = 0):
+    """Per-child reduction of a score table in table order (the consumers of Sec. 1):
+    for every child c, the minimum score, every parent mask reaching it, the natural
+    log of the sum of exp(-score) over all parent sets, and the top_k smallest scores
+    with their parent masks (ascending; equal scores in ascending mask order).
+    Plain loops over the table; returns a list of dicts, one per child."""
+    t = np.asarray(table, dtype=np.float64).reshape(m, -1)
+    out = []
+    for c in range(m):
+        row = t[c]
+        masks = np.array([family_decode(m, c * row.size + i)[1] for i in range(row.size)],
+                         dtype=np.int64)
+        mn = row.min()
+        best = [int(masks[i]) for i in range(row.size) if row[i] == mn]
+        # ln sum exp(-s) = -min + ln sum exp(min - s): every term is at most 1
+        lse = -mn + float(np.log(np.sum(np.exp(mn - row))))
+        order = sorted(range(row.size), key=lambda i: (row[i], masks[i]))[:top_k]
+        out.append({"min": float(mn), "argmin_masks": best, "logsumexp": lse,
+                    "top_scores": [float(row[i]) for i in order],
+                    "top_masks": [int(masks[i]) for i in order]})
+    return out

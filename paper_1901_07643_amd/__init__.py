@@ -19,11 +19,11 @@ import ctypes
 
 import numpy as np
 
-from ._abi import (BatchData, GS_EINVAL, GS_ENOTFINITE, GS_ERANGE, GS_ERANK, GS_MAX_M, GS_OK,
+from ._abi import (BatchData, ReduceOut, GS_EINVAL, GS_ENOTFINITE, GS_ERANGE, GS_ERANK, GS_MAX_M, GS_OK,
                    GS_OUT_BIC, GS_OUT_RSS, GivScoreError, PlanInfo, check, last_error, lib)
 
 __all__ = [
-    "Plan", "Batch", "score_all", "count_writes", "score_backward", "givscore", "GivScore", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
+    "Plan", "Batch", "score_all", "score_reduce", "count_writes", "score_backward", "givscore", "GivScore", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
     "GS_OK", "GS_EINVAL", "GS_ERANK", "GS_ENOTFINITE", "GS_ERANGE", "GS_MAX_M", "lib", "last_error",
 ]
 
@@ -172,6 +172,36 @@ def score_all(X, plan: Plan | None = None, what: str = "bic", precision: str = "
         if check_status:
             check(plan.status())
     return out
+
+
+def score_reduce(X, plan: Plan | None = None, top_k: int = 0, check_status: bool = True):
+    """Per-child results of the FP32 BIC walk without the score table (gs_score_reduce):
+    dict of device tensors best_score (m,) float32, best_parents (m,) int32 parent masks,
+    logsumexp (m,) float64 = ln sum_S exp(-BIC(c, S)), and with top_k > 0 top_score
+    (m, top_k) float32 ascending and top_parents (m, top_k) int32."""
+    import torch
+    n, m, ldx = _check_X(X, plan.m if plan else None)
+    plan = plan or Plan(m)
+    dev = X.device
+    res = {"best_score": torch.empty(m, dtype=torch.float32, device=dev),
+           "best_parents": torch.empty(m, dtype=torch.int32, device=dev),
+           "logsumexp": torch.empty(m, dtype=torch.float64, device=dev)}
+    o = ReduceOut()
+    o.best_score = res["best_score"].data_ptr()
+    o.best_parents = res["best_parents"].data_ptr()
+    o.logsumexp = res["logsumexp"].data_ptr()
+    o.top_k = int(top_k)
+    if top_k > 0:
+        res["top_score"] = torch.empty((m, top_k), dtype=torch.float32, device=dev)
+        res["top_parents"] = torch.empty((m, top_k), dtype=torch.int32, device=dev)
+        o.top_score = res["top_score"].data_ptr()
+        o.top_parents = res["top_parents"].data_ptr()
+    with torch.cuda.device(dev):
+        check(lib().gs_score_reduce(plan.handle, ctypes.c_void_p(X.data_ptr()), n, m, ldx,
+                                    ctypes.byref(o), _stream(dev)))
+        if check_status:
+            check(plan.status())
+    return res
 
 
 def count_writes(X, plan: Plan | None = None, out=None):

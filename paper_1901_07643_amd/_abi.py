@@ -33,6 +33,12 @@ class PlanInfo(ctypes.Structure):
     ]
 
 
+class ReduceOut(ctypes.Structure):
+    _fields_ = [("best_score", ctypes.c_void_p), ("best_parents", ctypes.c_void_p),
+                ("logsumexp", ctypes.c_void_p), ("top_score", ctypes.c_void_p),
+                ("top_parents", ctypes.c_void_p), ("top_k", ctypes.c_int)]
+
+
 class BatchData(ctypes.Structure):
     _fields_ = [("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("scores", ctypes.c_void_p)]
 
@@ -72,6 +78,7 @@ def lib():
         "gs_score_all": (i32, [vp, vp, i64, i32, i64, vp, i32, vp]),
         "gs_score_all_f64": (i32, [vp, vp, i64, i32, i64, vp, i32, vp]),
         "gs_count_writes": (i32, [vp, vp, i64, i32, i64, vp, vp]),
+        "gs_score_reduce": (i32, [vp, vp, i64, i32, i64, ctypes.POINTER(ReduceOut), vp]),
         "gs_score_all_static": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, vp]),
         "gs_score_backward": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
         "gs_score_backward_f64": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),

@@ -39,6 +39,12 @@ void free_device(gs_plan_s *p) {
     (void)hipFree(p->d_partial);
     (void)hipFree(p->d_B);
     (void)hipFree(p->d_K);
+    (void)hipFree(p->red.pmin);
+    (void)hipFree(p->red.pmask);
+    (void)hipFree(p->red.psum);
+    (void)hipFree(p->red.ptopv);
+    (void)hipFree(p->red.ptopm);
+    p->red = ReducePartials{};
     p->d_anchorbar = p->d_tailbar = p->d_vout = p->d_partial = p->d_B = p->d_K = nullptr;
     p->d_prog = nullptr;
     p->d_r0 = p->d_qr_a = p->d_qr_b = nullptr;
@@ -313,6 +319,51 @@ int gs_count_writes(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx
     hipError_t e = launch_walk_count(p, static_cast<const float *>(p->d_anchor),
                                      static_cast<const float *>(p->d_tail), counts, n, s);
     if (e != hipSuccess) return hip_fail(e, "walk launch");
+    if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    p->last_stream = s;
+    return GS_OK;
+}
+
+int gs_score_reduce(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx,
+                    const gs_reduce_t *out, void *stream) {
+    if (!out) return fail(GS_EINVAL, "gs_score_reduce: out is NULL");
+    int st = check_common(p, X, n, m, ldx, out->best_score, "gs_score_reduce");
+    if (st != GS_OK) return st;
+    if (!out->best_parents || !out->logsumexp)
+        return fail(GS_EINVAL, "gs_score_reduce: NULL output array");
+    if (out->top_k < 0 || out->top_k > GS_REDUCE_MAX_TOPK)
+        return fail(GS_EINVAL, "gs_score_reduce: top_k must be in 0..8");
+    if (out->top_k > 0 && (!out->top_score || !out->top_parents))
+        return fail(GS_EINVAL, "gs_score_reduce: top_k > 0 needs top_score and top_parents");
+    if ((st = ensure_workspace(p, n)) != GS_OK) return st;
+    if (!p->red.pmin) {
+        const size_t cnt = size_t(p->m) * size_t(p->nseg);
+        hipError_t e;
+        if ((e = hipMalloc(&p->red.pmin, cnt * 4)) != hipSuccess ||
+            (e = hipMalloc(&p->red.pmask, cnt * 4)) != hipSuccess ||
+            (e = hipMalloc(&p->red.psum, cnt * 4)) != hipSuccess ||
+            (e = hipMalloc(&p->red.ptopv, cnt * GS_REDUCE_TOPK * 4)) != hipSuccess ||
+            (e = hipMalloc(&p->red.ptopm, cnt * GS_REDUCE_TOPK * 4)) != hipSuccess) {
+            (void)hipFree(p->red.pmin);
+            (void)hipFree(p->red.pmask);
+            (void)hipFree(p->red.psum);
+            (void)hipFree(p->red.ptopv);
+            p->red = ReducePartials{};
+            return fail(GS_ENOMEM, std::string("reduction workspace: ") + hipGetErrorString(e));
+        }
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t *ev = new_event_set(p);
+    if ((st = front_half<float>(p, X, n, m, ldx, s, ev)) != GS_OK) return st;
+    const bool top = out->top_k > 0;
+    hipError_t e = launch_walk_reduce(p, static_cast<const float *>(p->d_anchor),
+                                      static_cast<const float *>(p->d_tail), p->red, top, n, s);
+    if (e != hipSuccess) return hip_fail(e, "reduce walk launch");
+    if ((e = launch_reduce_children(p, p->red, top, out->best_score, out->best_parents,
+                                    out->logsumexp, out->top_score, out->top_parents, out->top_k,
+                                    s)) != hipSuccess)
+        return hip_fail(e, "child merge launch");
+    if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     p->last_stream = s;
     return GS_OK;

@@ -36,6 +36,18 @@ struct ColStats {
 constexpr double GS_GUARD_VIF = 1e8;
 
 
+// Per (child, segment) partial results of the fused reduction (index child * nseg +
+// segment): the minimum BIC, its parent set, the sum of exp(min - BIC) over the
+// segment's parent sets, and (top-k mode) the GS_REDUCE_TOPK smallest values, ascending.
+#define GS_REDUCE_TOPK 8
+struct ReducePartials {
+    float *pmin = nullptr;
+    uint32_t *pmask = nullptr;
+    float *psum = nullptr;
+    float *ptopv = nullptr;
+    uint32_t *ptopm = nullptr;
+};
+
 struct gs_plan_s {
     uint64_t id = 0;  // unique per plan created in this process
     int m = 0, k = 0, ks = 0, q = 0;
@@ -67,6 +79,8 @@ struct gs_plan_s {
     double *d_partial = nullptr;    // chunks x m x m
     double *d_B = nullptr;          // m x m
     double *d_K = nullptr;          // m x m
+    // fused-reduction partials (allocated on the first gs_score_reduce call)
+    ReducePartials red;
     hipStream_t last_stream = nullptr;
     hipEvent_t done = nullptr;
 
@@ -185,6 +199,13 @@ hipError_t launch_walk_f32(const gs_plan_s *p, const float *anchor, const float 
                            int64_t n, bool bic, hipStream_t s);
 hipError_t launch_walk_f64(const gs_plan_s *p, const double *anchor, const double *tail,
                            double *out, int64_t n, bool bic, hipStream_t s);
+// The FP32 BIC walk folding its values into per (child, segment) partials instead of
+// writing the table (top: also the smallest GS_REDUCE_TOPK), then the per-child merge.
+hipError_t launch_walk_reduce(const gs_plan_s *p, const float *anchor, const float *tail,
+                              const ReducePartials &red, bool top, int64_t n, hipStream_t s);
+hipError_t launch_reduce_children(const gs_plan_s *p, const ReducePartials &red, bool top,
+                                  float *best, uint32_t *best_mask, double *lse, float *top_v,
+                                  uint32_t *top_m, int top_k, hipStream_t s);
 // The FP32 walk with every table write replaced by an atomic +1 of a uint32 counter.
 hipError_t launch_walk_count(const gs_plan_s *p, const float *anchor, const float *tail,
                              uint32_t *counts, int64_t n, hipStream_t s);

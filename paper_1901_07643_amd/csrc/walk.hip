@@ -159,6 +159,7 @@ __device__ __forceinline__ void givens_cs(T a, T b, T &c, T &s) {
 struct WalkArgs {
     int m, k, q;
     int64_t nseg, nsub, nwaves;
+    ReducePartials red;  // reduce modes only
     double row_scale;  // 1/sqrt(n) for BIC (the table then gets RSS/n inside the log), 1 for RSS
     double nlog;       // n ln 2 (FP32 path, log2 in hardware) or n (FP64 path)
     double lnn;        // ln n
@@ -275,7 +276,12 @@ __device__ __forceinline__ void count_line(T *dst) {
     for (int i = 0; i < CNT; ++i) atomicAdd(p + i, 1u);
 }
 
-enum WalkMode { WALK_STORE = 0, WALK_COUNT = 1 };
+// WALK_REDUCE / WALK_REDUCE_TOP: nothing is written to the table; every lane folds the
+// BIC values of its child into a running minimum (with its parent set), a running
+// sum of exp(min - BIC) and, for WALK_REDUCE_TOP, the GS_REDUCE_TOPK smallest values
+// (with their parent sets), and writes them per (child, segment) at the end.
+enum WalkMode { WALK_STORE = 0, WALK_COUNT = 1, WALK_REDUCE = 2, WALK_REDUCE_TOP = 3 };
+constexpr float REDUCE_SKIP = 30.0f;  // natural-log units
 
 constexpr int WALK_WAVES = 4;  // waves per workgroup
 #ifndef WALK_MIN_WAVES
@@ -343,6 +349,16 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
     const int ec2 = label >= 0 ? 2 * stats->exp2[label] : 0;
     const T coff = T(a.nln2 * double(ec2));
     bool out_of_range = false;  // RSS output only: a value outside the normal range
+    // reduce modes: running minimum, its parent set, sum of exp(min - BIC), top values
+    float rmin = __builtin_inff(), rsum = 0.0f;
+    uint32_t rmask = 0;
+    float tv[GS_REDUCE_TOPK];
+    uint32_t tm[GS_REDUCE_TOPK];
+#pragma unroll
+    for (int j = 0; j < GS_REDUCE_TOPK; ++j) {
+        tv[j] = __builtin_inff();
+        tm[j] = 0xffffffffu;
+    }
 
     int z = q;
     // One sub-walk: the transition into it, the inner walk, the table writes.  FWD is
@@ -445,6 +461,68 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
             sfx[J + 1] = ny * ny + sfx[J + 2];
             o[U] = score(sfx[J + 1], popcount_c(U));
         });
+
+        if constexpr (MODE == WALK_REDUCE || MODE == WALK_REDUCE_TOP) {
+            // fold this sub-walk's line into the lane's running reduction
+            constexpr float L2E = 1.4426950408889634f;
+            const uint32_t Shi32 = uint32_t(Fbits | (uint64_t(omask) << KS));
+            const bool is_child =
+                cls == 1 || cls == 3 || (cls == 2 && !((omask >> (lane - KS)) & 1u));
+            const uint32_t own = cls == 1 ? (1u << lane) : 0u;  // inner child: entries without it
+            float v[NS];
+            float lmin = __builtin_inff();
+            static_for<0, NS>([&](auto uc) {
+                constexpr int U = decltype(uc)::value;
+                v[U] = (is_child && !(U & own)) ? float(o[U]) : __builtin_inff();
+                lmin = fminf(v[U], lmin);
+            });
+            // Lines whose values all lie more than REDUCE_SKIP above the lane's running
+            // minimum add less than e^-REDUCE_SKIP each to the sum of exp(min - BIC) (at
+            // most 2^18 per lane and segment: below 3e-8 of the sum, which is >= 1); a
+            // wave skips the line when no lane has a value within that distance.
+            if (__builtin_amdgcn_ballot_w64(lmin < rmin + REDUCE_SKIP) != 0) {
+                const float nm = fminf(rmin, lmin);
+                if (__builtin_amdgcn_ballot_w64(lmin < rmin) != 0) {
+                    int lU = 0;  // the first entry reaching the line minimum
+                    static_for<0, NS>([&](auto uc) {
+                        constexpr int U = NS - 1 - decltype(uc)::value;
+                        lU = v[U] == lmin ? U : lU;
+                    });
+                    rmask = lmin < rmin ? (Shi32 | uint32_t(lU)) : rmask;
+                }
+                float ls = 0.0f;
+                static_for<0, NS>([&](auto uc) {
+                    constexpr int U = decltype(uc)::value;
+                    ls += __builtin_amdgcn_exp2f((nm - v[U]) * L2E);
+                });
+                if (is_child) {
+                    rsum = rsum * __builtin_amdgcn_exp2f((nm - rmin) * L2E) + ls;
+                    rmin = nm;
+                }
+            }
+            if constexpr (MODE == WALK_REDUCE_TOP) {
+                if (__builtin_amdgcn_ballot_w64(lmin < tv[GS_REDUCE_TOPK - 1]) != 0) {
+                    static_for<0, NS>([&](auto uc) {
+                        constexpr int U = decltype(uc)::value;
+                        float cv = v[U];
+                        if (cv < tv[GS_REDUCE_TOPK - 1]) {
+                            uint32_t cm = Shi32 | uint32_t(U);
+                            static_for<0, GS_REDUCE_TOPK>([&](auto jc) {
+                                constexpr int j = decltype(jc)::value;
+                                const bool sw = cv < tv[j];
+                                const float ov = tv[j];
+                                const uint32_t om = tm[j];
+                                tv[j] = sw ? cv : ov;
+                                tm[j] = sw ? cm : om;
+                                cv = sw ? ov : cv;
+                                cm = sw ? om : cm;
+                            });
+                        }
+                    });
+                }
+            }
+            return;
+        }
 
         // write this sub-walk's table lines
         const uint64_t Shi = Fbits | (uint64_t(omask) << KS);
@@ -553,19 +631,36 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
     // guarded path.
     if (std::is_same_v<T, double> || (status[0] & GS_FLAG_GUARD)) run(std::true_type{});
     else run(std::false_type{});
+    if constexpr (MODE == WALK_REDUCE || MODE == WALK_REDUCE_TOP) {
+        if (seg_ok && cls != 0) {
+            const int64_t r = int64_t(label) * a.nseg + segv;
+            a.red.pmin[r] = rmin;
+            a.red.pmask[r] = rmask;
+            a.red.psum[r] = rsum;
+            if constexpr (MODE == WALK_REDUCE_TOP) {
+#pragma unroll
+                for (int j = 0; j < GS_REDUCE_TOPK; ++j) {
+                    a.red.ptopv[r * GS_REDUCE_TOPK + j] = tv[j];
+                    a.red.ptopm[r * GS_REDUCE_TOPK + j] = tm[j];
+                }
+            }
+        }
+    }
     if constexpr (!BIC) {
         if (__builtin_amdgcn_ballot_w64(out_of_range && seg_ok) != 0 && lane64 == 0)
             atomicOr(const_cast<int *>(status), GS_FLAG_RANGE);
     }
 }
 
-template <typename T, int KS>
+template <typename T, int KS, int MODE = WALK_STORE>
 __host__ __device__ constexpr size_t walk_stage_bytes() {
-    return (std::is_same_v<T, float> && KS == 5) ? size_t(STAGE_BYTES) : 0;
+    return (std::is_same_v<T, float> && KS == 5 && (MODE == WALK_STORE || MODE == WALK_COUNT))
+               ? size_t(STAGE_BYTES)
+               : 0;
 }
-template <typename T, int KS>
+template <typename T, int KS, int MODE = WALK_STORE>
 __host__ __device__ constexpr size_t walk_wave_lds(int q) {
-    return walk_stage_bytes<T, KS>() + size_t(q > 0 ? q : 1) * 64 * sizeof(T);
+    return walk_stage_bytes<T, KS, MODE>() + size_t(q > 0 ? q : 1) * 64 * sizeof(T);
 }
 
 template <typename T, int KS, bool BIC, int MINW, int MODE = WALK_STORE>
@@ -578,8 +673,8 @@ void walk_kernel(const T *__restrict__ anchor, const T *__restrict__ tail,
     extern __shared__ float4 lds_walk[];
     const int wave = threadIdx.x >> 6;
     const int64_t wid = int64_t(blockIdx.x) * WALK_WAVES + wave;
-    char *base = reinterpret_cast<char *>(lds_walk) + wave * walk_wave_lds<T, KS>(a.q);
-    constexpr size_t stage = walk_stage_bytes<T, KS>();
+    char *base = reinterpret_cast<char *>(lds_walk) + wave * walk_wave_lds<T, KS, MODE>(a.q);
+    constexpr size_t stage = walk_stage_bytes<T, KS, MODE>();
     float4 *Sg = reinterpret_cast<float4 *>(base);
     uint64_t *Dg = reinterpret_cast<uint64_t *>(base + STAGE_LINES * STAGE_CHUNKS * 16);
     walk_body<T, KS, BIC, MODE>(anchor, tail, prog, lane_seg, lane_loc, status, stats, out, a, wid,
@@ -623,11 +718,16 @@ void walk_batched_kernel(const BatchItem *__restrict__ items, const int32_t *__r
 // (5 waves per SIMD); the others take what they need.
 template <typename T, int KS>
 constexpr int kMinWaves = !std::is_same_v<T, float> ? 1 : (KS == 5 ? 4 : (KS < 5 ? WALK_MIN_WAVES : 1));
+// the top-k reduction keeps 16 more values per lane and has no line stage: 168 VGPRs
+template <typename T, int KS, int MODE>
+constexpr int kMinWavesMode = (MODE == WALK_REDUCE_TOP && KS == 5) ? 3 : kMinWaves<T, KS>;
 
 template <typename T, bool BIC, int MODE = WALK_STORE>
 static hipError_t launch_walk_t(const gs_plan_s *p, const WalkTables &t, const T *anchor,
-                                const T *tail, T *out, int64_t n, hipStream_t s) {
+                                const T *tail, T *out, int64_t n, hipStream_t s,
+                                const ReducePartials *red = nullptr) {
     WalkArgs a;
+    a.red = red ? *red : ReducePartials{};
     a.m = p->m;
     a.k = p->k;
     a.q = p->q;
@@ -641,11 +741,13 @@ static hipError_t launch_walk_t(const gs_plan_s *p, const WalkTables &t, const T
     a.nln2 = dn * 0.6931471805599453;
     const dim3 grid(unsigned((p->nwaves + WALK_WAVES - 1) / WALK_WAVES));
     const dim3 block(64 * WALK_WAVES);
-    const size_t lds = WALK_WAVES * (p->ks == 5 ? walk_wave_lds<T, 5>(p->q) : walk_wave_lds<T, 1>(p->q));
+    const size_t lds = WALK_WAVES * (p->ks == 5 ? walk_wave_lds<T, 5, MODE>(p->q)
+                                                : walk_wave_lds<T, 1, MODE>(p->q));
     switch (p->ks) {
 #define GS_WALK_CASE(KSV)                                                                   \
     case KSV:                                                                               \
-        hipLaunchKernelGGL((walk_kernel<T, KSV, BIC, kMinWaves<T, KSV>, MODE>), grid, block, lds, \
+        hipLaunchKernelGGL((walk_kernel<T, KSV, BIC, kMinWavesMode<T, KSV, MODE>, MODE>), grid,  \
+                           block, lds,                                                         \
                            s,                                                                  \
                            anchor, tail,                                                    \
                            t.prog, t.lane_seg, t.lane_loc, t.status, t.stats, out, a);      \
@@ -696,6 +798,14 @@ hipError_t launch_walk_count(const gs_plan_s *p, const float *anchor, const floa
                              uint32_t *counts, int64_t n, hipStream_t s) {
     return launch_walk_t<float, true, WALK_COUNT>(p, plan_tables(p), anchor, tail,
                                                   reinterpret_cast<float *>(counts), n, s);
+}
+
+hipError_t launch_walk_reduce(const gs_plan_s *p, const float *anchor, const float *tail,
+                              const ReducePartials &red, bool top, int64_t n, hipStream_t s) {
+    return top ? launch_walk_t<float, true, WALK_REDUCE_TOP>(p, plan_tables(p), anchor, tail,
+                                                             nullptr, n, s, &red)
+               : launch_walk_t<float, true, WALK_REDUCE>(p, plan_tables(p), anchor, tail, nullptr,
+                                                         n, s, &red);
 }
 
 hipError_t launch_walk_f64(const gs_plan_s *p, const double *anchor, const double *tail,

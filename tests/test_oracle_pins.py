@@ -221,3 +221,30 @@ def test_gram_route_agrees_with_householder(m, n, seed):
             assert np.max(np.abs(a - b) / a) <= 1e-12
         else:
             assert np.max(np.abs(a - b)) <= 1e-9
+
+
+# ---- the per-child reduction of a table (the fused consumer's reference)
+
+def test_reduce_table_pins():
+    """Minimum and argmin by brute force over the families, logsumexp against scipy,
+    top-k against a full sort, on the oracle's own BIC table."""
+    from scipy.special import logsumexp
+    m, n = 6, 50
+    X = linear_gaussian(m, n, 0.4, 0.5, 1.5, seed=31)
+    T = oracle.score_all(X, oracle.OUT_BIC, threads=2)
+    red = oracle.reduce_table(T, m, top_k=5)
+    for c in range(m):
+        vals = {_mask(S): T[oracle.family_index(m, c, _mask(S))] for cc, S in _families(m) if cc == c}
+        mn = min(vals.values())
+        assert red[c]["min"] == mn
+        assert sorted(red[c]["argmin_masks"]) == sorted(k for k, v in vals.items() if v == mn)
+        assert red[c]["logsumexp"] == pytest.approx(logsumexp([-v for v in vals.values()]), rel=1e-14)
+        srt = sorted(vals.items(), key=lambda kv: (kv[1], kv[0]))[:5]
+        assert red[c]["top_masks"] == [k for k, _ in srt]
+        assert red[c]["top_scores"] == [v for _, v in srt]
+    # ties: every mask reaching the minimum is reported
+    T2 = np.zeros(oracle.num_families(3))
+    T2[[0, 3]] = -1.0
+    r2 = oracle.reduce_table(T2, 3, top_k=2)
+    assert r2[0]["argmin_masks"] == [0, 0b110] and r2[0]["top_masks"] == [0, 0b110]
+    assert r2[1]["logsumexp"] == pytest.approx(np.log(4.0))
