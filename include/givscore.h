@@ -79,11 +79,13 @@ typedef struct {
     int64_t num_waves;          /* 64-lane waves the segments are packed into         */
 } gs_plan_info_t;
 
-/* Number of families m * 2^(m-1); -1 if m is outside 1..GS_MAX_M. */
+/* Number of families m * 2^(m-1) (Sec. 1: every child with every subset of the other
+ * m - 1 variables, the empty set included); -1 if m is outside 1..GS_MAX_M. */
 int64_t gs_num_families(int m);
 
-/* Table index of (child, parent_mask); -1 if child is out of range, bit `child`
- * is set in parent_mask, or parent_mask has bits at or above m. */
+/* Table index of (child, parent_mask) in the layout above (the paper's score table of
+ * Sec. 1 and Sec. 3 has no stated order; this is the library's); -1 if child is out of
+ * range, bit `child` is set in parent_mask, or parent_mask has bits at or above m. */
 int64_t gs_family_index(int m, int child, uint64_t parent_mask);
 
 /* The paper's swap sequence Upsilon(m) (Sec. 3 recursion with the "+1" shift,
@@ -92,17 +94,24 @@ int64_t gs_family_index(int m, int child, uint64_t parent_mask);
  * or GS_EINVAL for m outside 1..24. */
 int64_t gs_upsilon(int m, int32_t *out, int64_t cap);
 
-/* Create a plan for m variables (1..GS_MAX_M) with the default segment sizes.
- * Host-only integer work; no device memory is touched until the first score call.
- * *out receives a library-owned handle. */
+/* Create a plan for m variables (1..GS_MAX_M) with the default segment sizes: the
+ * split of Sec. 6 / Alg. 2 into 2^(m-k) independent segments, each walking k
+ * variables along Upsilon(k) (Sec. 3) with the other m - k fixed in front or behind,
+ * packed into 64-lane waves.  Host-only integer work; no device memory is touched
+ * until the first score call.  *out receives a library-owned handle. */
 int gs_plan(int m, gs_plan_t **out);
 
-/* Same with explicit sizes: 1 <= ks <= 6, ks <= m, ks <= k <= m, k - ks <= 16.
- * ks = 0 or k = 0 selects the default for that size. */
+/* Same with explicit sizes (Sec. 6: k walked variables per segment; ks the inner
+ * block walked by Upsilon(ks) at every resting point of the middle variables):
+ * 1 <= ks <= 6, ks <= m, ks <= k <= m, k - ks <= 16.  ks = 0 or k = 0 selects the
+ * default for that size.  Lanes per segment and waves per CU are not parameters: a
+ * segment takes one lane per column it walks or carries (k + its back variables),
+ * segments are packed side by side into 64-lane waves, and the kernels' register and
+ * LDS budgets fix the waves per CU (4 per SIMD for the FP32 walk with ks = 5). */
 int gs_plan_tuned(int m, int k, int ks, gs_plan_t **out);
 
-/* Free a plan and its device workspace (NULL is ignored).  The device work it
- * enqueued must have finished. */
+/* Free a plan and its device workspace (NULL is ignored); waits for the plan's last
+ * enqueued work. */
 void gs_plan_destroy(gs_plan_t *plan);
 
 /* Device bytes the plan's workspace takes for data of n rows (backward != 0: including
@@ -111,12 +120,14 @@ void gs_plan_destroy(gs_plan_t *plan);
  * exceed it fail with GS_ENOMEM before touching the device. */
 int gs_plan_workspace_bytes(const gs_plan_t *plan, int64_t n, int backward, int64_t *bytes);
 
-/* Sizes chosen by the plan (host struct). */
+/* Sizes chosen by the plan (host struct; Sec. 6 segment split, Sec. 3 sequence
+ * lengths). */
 int gs_plan_get_info(const gs_plan_t *plan, gs_plan_info_t *info);
 
 /* Host simulation of the plan's walk: counts[index] += 1 for every family the
- * kernels will write (counts: host, len >= m * 2^(m-1)).  A correct plan leaves
- * every entry incremented exactly once.  For testing the planner; m <= 22. */
+ * kernels will write (counts: host, len >= m * 2^(m-1)).  The split of Sec. 6 covers
+ * every family exactly once, so a correct plan leaves every entry at 1.  For testing
+ * the planner; m <= 22 (gs_count_writes checks the kernels at any size). */
 int gs_plan_count_emissions(const gs_plan_t *plan, int32_t *counts, int64_t len);
 
 /* R0 = the triangular factor of the QR decomposition of X (Sec. 2, the initial
@@ -126,7 +137,11 @@ int gs_plan_count_emissions(const gs_plan_t *plan, int32_t *counts, int64_t len)
 int gs_qr_r0(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
              double *R0, void *stream);
 
-/* Scores of all m * 2^(m-1) families with the walk in FP32 (segment starts in FP64).
+/* Scores of all m * 2^(m-1) families (Sec. 1) by the walk: one QRD of X (Sec. 2),
+ * then the shortest sequence of adjacent column swaps, each retriangularised by one
+ * Givens rotation (Sec. 1.3, Sec. 3-4), every visited R read out as the RSS of its
+ * prefix regressions (Sec. 2), split into independent segments (Sec. 6).  The walk
+ * runs in FP32; R0 and each segment's starting R are FP64.
  *   X: device, n x m row-major FP64, row stride ldx >= m, n > m; m must equal the
  *      plan's m.
  *   scores: device, m * 2^(m-1) floats, 16-byte aligned, written in table order
@@ -193,7 +208,7 @@ int gs_score_all_static(gs_plan_t *plan, const double *X, int64_t n, int m, int6
 int gs_count_writes(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
                     uint32_t *counts, void *stream);
 
-/* Same, with the whole walk in FP64 and an FP64 table (16-byte aligned). */
+/* Same method with the whole walk in FP64 and an FP64 table (16-byte aligned). */
 int gs_score_all_f64(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
                      double *scores, int what, void *stream);
 
@@ -231,8 +246,8 @@ int gs_sync_status(gs_plan_t *plan);
  * exact arithmetic. */
 int gs_column_vif(gs_plan_t *plan, double *vif);
 
-/* Per-stage timing with HIP events recorded on the call's stream.  enable != 0
- * starts recording (and clears old records). */
+/* Measurement: per-stage timing with HIP events recorded on the call's stream.
+ * enable != 0 starts recording (and clears old records). */
 int gs_set_timing(gs_plan_t *plan, int enable);
 
 /* Waits for the recorded events and returns, for the calls recorded since the last

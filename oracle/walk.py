@@ -19,18 +19,23 @@ __all__ = [
 
 
 def greedy_swaps(m: int) -> list[int]:
-    """Upsilon(m) from the recursion of Sec. 3 / Sec. 5:
-    Upsilon(2) = [1];  Upsilon(m) = Upsilon(m-1) : [m-1, ..., 1] : [i+1 for i in Upsilon(m-1)].
-    The "+1" on the last block is the text's reading (Alg. 1 as printed omits it).
-    Upsilon(1) is empty (one variable: the initial QRD already solves everything)."""
+    """Upsilon(m), the shortest swap sequence of Sec. 3, built from what the section
+    describes: with the last variable kept at the back, the first m - 1 variables are
+    walked through their own sequence (every parent set of them is then a prefix once);
+    the last variable is carried from the back to the front by m - 1 adjacent swaps
+    (positions m - 1 down to 1); the first m - 1 are walked through their sequence once
+    more, now one position further right, behind it (every parent set that holds it).
+    The second walk's positions are shifted by one, as the text and the Sec. 5
+    recurrence say.  One variable needs no swap; two need one."""
     if m < 1:
         raise ValueError("m >= 1")
     if m == 1:
         return []
     if m == 2:
         return [1]
-    prev = greedy_swaps(m - 1)
-    return prev + list(range(m - 1, 0, -1)) + [i + 1 for i in prev]
+    rest = greedy_swaps(m - 1)
+    carry_to_front = list(range(m - 1, 0, -1))
+    return rest + carry_to_front + [i + 1 for i in rest]
 
 
 def swap_count(m: int) -> int:
@@ -108,23 +113,22 @@ def runtime_T_closed(m: int) -> int:
 
 
 def seed_path(code_bits: list[int], m: int):
-    """Alg. 2 (SeedPathCalculator) as read: the processor code has len(code) bits,
-    k = m - len(code) variables are walked with Upsilon(k) shifted by d, where d
-    is the number of variables inserted at the front.  Loop bound is m (printed
-    as n).  Bit P[m-i] == 0 inserts variable i at the front, else appends it.
-    Variables are 1-based labels.  Returns (initial ordering, swap list)."""
+    """A processor's share of the walk (Sec. 6): its code fixes each of the outer
+    variables k + 1 .. m (1-based labels, k = m - len(code)) either in front of the
+    walked block, where it is a parent of every family the processor emits, or behind
+    it, where it never is.  Variable i reads code bit m - i; 0 puts it in front (the
+    polarity Alg. 2 prints).  The processor's initial ordering is the front set (later
+    labels nearer the front), the walked variables 1 .. k, then the back set (in
+    label order); it walks Upsilon(k) on the walked block, i.e. every swap index
+    shifted by the size d of the front set.  Returns (initial ordering, swap list)."""
     k = m - len(code_bits)
     if k < 1:
         raise ValueError("code longer than m - 1")
-    order = list(range(1, k + 1))
-    front = 0
-    for i in range(k + 1, m + 1):
-        if code_bits[m - i] == 0:
-            order.insert(0, i)
-            front += 1
-        else:
-            order.append(i)
-    return order, [front + s for s in greedy_swaps(k)]
+    outer = list(range(k + 1, m + 1))
+    front = [i for i in reversed(outer) if code_bits[m - i] == 0]
+    back = [i for i in outer if code_bits[m - i] != 0]
+    d = len(front)
+    return front + list(range(1, k + 1)) + back, [d + s for s in greedy_swaps(k)]
 
 
 def num_families(m: int) -> int:
