@@ -439,3 +439,25 @@ def test_workspace_cap(gs, monkeypatch):
     monkeypatch.setenv("GS_WORKSPACE_LIMIT", str(need))
     got = gs.score_all(Xd, plan=plan, what="rss", precision="fp64").cpu().numpy()
     _assert_rss(got, oracle.score_all(X, oracle.OUT_RSS), TOL["fp64"], "capped workspace")
+
+
+@pytest.mark.parametrize("delta", [1.0, 1e-2, 3e-4, 1e-4, 1e-5])
+def test_fp64_walk_across_conditioning(gs, delta):
+    """The FP64 walk keeps 1e-10 from well-conditioned data to a largest VIF of about
+    1e11 (delta = 1e-5; the walks take their guarded steps above 1e8), with
+    R0^T R0 = X^T X to rounding throughout."""
+    m, n = 12, 300
+    X = linear_gaussian(m, n, 0.2, 0.5, 1.5, seed=1212)
+    v = X[:, 11] / np.linalg.norm(X[:, 11]) * np.linalg.norm(X[:, 0])
+    X[:, 11] = X[:, 0] + delta * v
+    X -= X.mean(axis=0)
+    plan = gs.Plan(m)
+    got = _run_plan_nocheck(gs, X, "rss", "fp64", plan).cpu().numpy()
+    V = float(plan.vif().max())
+    err = _assert_rss(got, oracle.score_all(X, oracle.OUT_RSS), TOL["fp64"], f"delta {delta:g}")
+    R = gs.qr_r0(torch.as_tensor(X, device="cuda"), plan=plan).cpu().numpy()
+    G = X.T @ X
+    gerr = np.abs(R.T @ R - G).max() / np.abs(G).max()
+    print(f"\ndelta {delta:g}: max VIF {V:.3e}, FP64 walk max rel RSS err {err:.3e}, "
+          f"|R0^T R0 - X^T X| / |X^T X| {gerr:.2e}")
+    assert gerr <= 1e-14
