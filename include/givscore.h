@@ -208,6 +208,20 @@ int gs_score_all_static(gs_plan_t *plan, const double *X, int64_t n, int m, int6
 int gs_count_writes(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
                     uint32_t *counts, void *stream);
 
+/* Regression coefficients of every family: Sec. 1.1 solves a regression from its QRD
+ * by back-substitution, O(|S|^2), and every R the walk visits is the QRD of its column
+ * ordering, so each family takes its coefficients from the R that solves it (Sec. 2):
+ * R[P][P] beta = R[P][c] for the prefix P.  FP64 walk over segments of up to 10
+ * variables (Sec. 6 split), R0 and segment starts as for the scores.
+ *   beta: device, m * 2^(m-1) rows of m doubles, row index(c, S) (table order): beta_v
+ *     for v in S, zeros elsewhere (the child included), so x_c - X beta_row is the
+ *     residual whose squared norm is RSS(c, S).  16-byte aligned; 8 m^2 2^(m-1) bytes
+ *     (1.7 GB at m = 20), hence m <= GS_BETA_MAX_M.
+ * The plan's m must equal m (its segment sizes are not used). */
+#define GS_BETA_MAX_M 22
+int gs_score_beta(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
+                  double *beta, void *stream);
+
 /* Same method with the whole walk in FP64 and an FP64 table (16-byte aligned). */
 int gs_score_all_f64(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
                      double *scores, int what, void *stream);

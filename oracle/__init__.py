@@ -49,6 +49,8 @@ def _lib():
         lib.or_score_all_gram.argtypes = [vp, i64, ctypes.c_int, i64, vp, ctypes.c_int,
                                           ctypes.c_int]
         lib.or_score_all_gram.restype = ctypes.c_int
+        lib.or_beta_all.argtypes = [vp, i64, ctypes.c_int, i64, vp, ctypes.c_int]
+        lib.or_beta_all.restype = ctypes.c_int
         lib.or_grad_from_gbar.argtypes = [vp, i64, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int]
         lib.or_grad_from_gbar.restype = ctypes.c_int
         _LIB = lib
@@ -126,6 +128,19 @@ def score_indices(X, idx, what: int = OUT_BIC, threads: int | None = None) -> np
                                  out.ctypes.data, what, threads or default_threads())
     if st != 0:
         raise RuntimeError(f"oracle score_indices failed ({st})")
+    return out
+
+
+def beta_all(X, threads: int | None = None) -> np.ndarray:
+    """Regression coefficients of every family (Sec. 1.1: back-substitution on the R of
+    the family's own Householder QR), (m * 2^(m-1), m) in table order: row idx holds
+    beta_v for the parents v of family idx and zeros elsewhere (the child included)."""
+    X = _as_X(X)
+    n, m = X.shape
+    out = np.empty((num_families(m), m), dtype=np.float64)
+    st = _lib().or_beta_all(X.ctypes.data, n, m, m, out.ctypes.data, threads or default_threads())
+    if st != 0:
+        raise RuntimeError(f"oracle beta_all failed ({st})")
     return out
 
 

@@ -353,6 +353,62 @@ static void beta_householder(const double *X, int64_t n, int m, int64_t ldx, int
     for (int i = 0; i < s; ++i) beta_full[cols[i]] = bl[i];
 }
 
+/* Coefficients of every family, table order: out[idx * m + v] = beta_v of family idx
+ * (zero for v outside the parent set, and for v = the child). */
+typedef struct {
+    const double *X;
+    int64_t n;
+    int m;
+    int64_t ldx;
+    int64_t begin, end;
+    double *out;
+    int status;
+} bjob_t;
+
+static void *run_bjob(void *p) {
+    bjob_t *jb = (bjob_t *)p;
+    double *work = (double *)malloc(sizeof(double) * (size_t)jb->n * (size_t)(jb->m + 1));
+    if (!work) {
+        jb->status = -3;
+        return NULL;
+    }
+    for (int64_t t = jb->begin; t < jb->end; ++t) {
+        int c;
+        uint64_t mask;
+        or_family_decode(jb->m, t, &c, &mask);
+        beta_householder(jb->X, jb->n, jb->m, jb->ldx, c, mask, work, jb->out + t * jb->m);
+    }
+    free(work);
+    return NULL;
+}
+
+int or_beta_all(const double *X, int64_t n, int m, int64_t ldx, double *out, int nthreads) {
+    if (!X || !out || n < 1 || m < 1 || m > 40 || ldx < m) return -1;
+    const int64_t N = or_num_families(m);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 64) nthreads = 64;
+    if (N < nthreads) nthreads = (int)N;
+    pthread_t th[64];
+    bjob_t jobs[64];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (bjob_t){X, n, m, ldx, N * t / nthreads, N * (t + 1) / nthreads, out, 0};
+        if (nthreads > 1) {
+            if (pthread_create(&th[t], NULL, run_bjob, &jobs[t]) != 0) {
+                run_bjob(&jobs[t]);
+                th[t] = 0;
+            }
+        } else {
+            run_bjob(&jobs[t]);
+        }
+    }
+    int st = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        if (nthreads > 1 && th[t]) pthread_join(th[t], NULL);
+        if (jobs[t].status) st = jobs[t].status;
+    }
+    return st;
+}
+
 typedef struct {
     const double *X;
     int64_t n;

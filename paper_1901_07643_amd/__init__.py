@@ -23,7 +23,7 @@ from ._abi import (BatchData, ReduceOut, GS_EINVAL, GS_ENOTFINITE, GS_ERANGE, GS
                    GS_OUT_BIC, GS_OUT_RSS, GivScoreError, PlanInfo, check, last_error, lib)
 
 __all__ = [
-    "Plan", "Batch", "score_all", "score_reduce", "count_writes", "score_backward", "givscore", "GivScore", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
+    "Plan", "Batch", "score_all", "score_reduce", "score_beta", "count_writes", "score_backward", "givscore", "GivScore", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
     "GS_OK", "GS_EINVAL", "GS_ERANK", "GS_ENOTFINITE", "GS_ERANGE", "GS_MAX_M", "lib", "last_error",
 ]
 
@@ -202,6 +202,26 @@ def score_reduce(X, plan: Plan | None = None, top_k: int = 0, check_status: bool
         if check_status:
             check(plan.status())
     return res
+
+
+def score_beta(X, plan: Plan | None = None, out=None, check_status: bool = True):
+    """Regression coefficients of every family (gs_score_beta): a (m * 2^(m-1), m) float64
+    device tensor in table order, row index(c, S) holding beta_v for v in S and zeros
+    elsewhere.  m <= 22."""
+    import torch
+    n, m, ldx = _check_X(X, plan.m if plan else None)
+    plan = plan or Plan(m)
+    N = num_families(m)
+    if out is None:
+        out = torch.empty((N, m), dtype=torch.float64, device=X.device)
+    elif out.shape != (N, m) or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous (m*2^(m-1), m) float64 tensor")
+    with torch.cuda.device(X.device):
+        check(lib().gs_score_beta(plan.handle, ctypes.c_void_p(X.data_ptr()), n, m, ldx,
+                                  ctypes.c_void_p(out.data_ptr()), _stream(X.device)))
+        if check_status:
+            check(plan.status())
+    return out
 
 
 def count_writes(X, plan: Plan | None = None, out=None):

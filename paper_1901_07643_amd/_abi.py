@@ -78,6 +78,7 @@ def lib():
         "gs_score_all": (i32, [vp, vp, i64, i32, i64, vp, i32, vp]),
         "gs_score_all_f64": (i32, [vp, vp, i64, i32, i64, vp, i32, vp]),
         "gs_count_writes": (i32, [vp, vp, i64, i32, i64, vp, vp]),
+        "gs_score_beta": (i32, [vp, vp, i64, i32, i64, vp, vp]),
         "gs_score_reduce": (i32, [vp, vp, i64, i32, i64, ctypes.POINTER(ReduceOut), vp]),
         "gs_score_all_static": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, vp]),
         "gs_score_backward": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build", "givscore")
 LIB = os.path.join(HERE, "libgivscore.so")
 SOURCES = ["plan.cpp", "capi.cpp", "batch.cpp", "qr.hip", "anchor.hip", "walk.hip", "adjoint.hip",
-           "static_ws.hip", "reduce.hip"]
+           "static_ws.hip", "reduce.hip", "beta.hip"]
 ARCH = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are switched off for all device code.

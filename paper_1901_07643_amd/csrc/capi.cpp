@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
+#include <vector>
 #include <string>
 
 #include "gs_internal.hpp"
@@ -39,6 +41,9 @@ void free_device(gs_plan_s *p) {
     (void)hipFree(p->d_partial);
     (void)hipFree(p->d_B);
     (void)hipFree(p->d_K);
+    (void)hipFree(p->d_ups);
+    p->d_ups = nullptr;
+    p->beta_k = 0;
     (void)hipFree(p->red.pmin);
     (void)hipFree(p->red.pmask);
     (void)hipFree(p->red.psum);
@@ -364,6 +369,41 @@ int gs_score_reduce(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx
                                     s)) != hipSuccess)
         return hip_fail(e, "child merge launch");
     if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    p->last_stream = s;
+    return GS_OK;
+}
+
+int gs_score_beta(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx, double *beta,
+                  void *stream) {
+    int st = check_common(p, X, n, m, ldx, beta, "gs_score_beta");
+    if (st != GS_OK) return st;
+    if (m > GS_BETA_MAX_M) return fail(GS_EINVAL, "gs_score_beta: m must be at most 22");
+    if ((st = ensure_workspace(p, n)) != GS_OK) return st;
+    const int k = m < 10 ? m : 10;
+    hipError_t e;
+    if (!p->d_ups || p->beta_k != k) {
+        std::vector<int> seq;
+        upsilon0(k, seq);
+        std::vector<int8_t> s8(seq.begin(), seq.end());
+        (void)hipFree(p->d_ups);
+        p->d_ups = nullptr;
+        if ((e = hipMalloc(&p->d_ups, std::max<size_t>(s8.size(), 1))) != hipSuccess)
+            return fail(GS_ENOMEM, std::string("coefficient walk program: ") + hipGetErrorString(e));
+        if (!s8.empty() &&
+            (e = hipMemcpy(p->d_ups, s8.data(), s8.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "coefficient walk program upload");
+        p->beta_k = k;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if ((e = launch_front_reset(p->d_status, p->d_stats, 1, s)) != hipSuccess)
+        return hip_fail(e, "status reset launch");
+    if ((e = launch_qr_r0(X, n, m, ldx, p->d_r0, nullptr, p->d_qr_a, p->d_qr_b, p->d_status,
+                          p->d_stats, s)) != hipSuccess)
+        return hip_fail(e, "R0 QR launch");
+    const int64_t nups = (int64_t(1) << k) - k - 1;
+    if ((e = launch_beta_walk(p->d_r0, p->d_stats, m, k, p->d_ups, nups, beta, s)) != hipSuccess)
+        return hip_fail(e, "coefficient walk launch");
     if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     p->last_stream = s;
     return GS_OK;

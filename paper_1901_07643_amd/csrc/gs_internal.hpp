@@ -81,6 +81,9 @@ struct gs_plan_s {
     double *d_K = nullptr;          // m x m
     // fused-reduction partials (allocated on the first gs_score_reduce call)
     ReducePartials red;
+    // coefficient walk: Upsilon(beta_k) on the device (first gs_score_beta call)
+    int8_t *d_ups = nullptr;
+    int beta_k = 0;
     hipStream_t last_stream = nullptr;
     hipEvent_t done = nullptr;
 
@@ -124,6 +127,8 @@ int hip_fail(hipError_t e, const char *what);
 
 // Host planner (plan.cpp)
 int build_program(gs_plan_s *p);
+// Upsilon(q) with 0-based swap positions (the paper's sequence minus one).
+void upsilon0(int q, std::vector<int> &seq);
 
 // One workgroup of a batched TSQR pass: rows [128 block, 128 block + 128) of A.
 struct TsqrJob {
@@ -206,6 +211,10 @@ hipError_t launch_walk_reduce(const gs_plan_s *p, const float *anchor, const flo
 hipError_t launch_reduce_children(const gs_plan_s *p, const ReducePartials &red, bool top,
                                   float *best, uint32_t *best_mask, double *lse, float *top_v,
                                   uint32_t *top_m, int top_k, hipStream_t s);
+// Coefficients of every family by an FP64 walk over segments of k variables (ups:
+// Upsilon(k), 0-based), out: m * 2^(m-1) rows of m doubles.
+hipError_t launch_beta_walk(const double *R0, const ColStats *stats, int m, int k,
+                            const int8_t *ups, int64_t nups, double *out, hipStream_t s);
 // The FP32 walk with every table write replaced by an atomic +1 of a uint32 counter.
 hipError_t launch_walk_count(const gs_plan_s *p, const float *anchor, const float *tail,
                              uint32_t *counts, int64_t n, hipStream_t s);

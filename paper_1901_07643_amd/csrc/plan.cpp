@@ -44,7 +44,7 @@ int hip_fail(hipError_t e, const char *what) {
     return GS_EHIP;
 }
 
-static void upsilon0(int q, std::vector<int> &seq) {
+void upsilon0(int q, std::vector<int> &seq) {
     seq.clear();
     if (q >= 2) seq.push_back(0);
     for (int kk = 3; kk <= q; ++kk) {

@@ -248,3 +248,22 @@ def test_reduce_table_pins():
     r2 = oracle.reduce_table(T2, 3, top_k=2)
     assert r2[0]["argmin_masks"] == [0, 0b110] and r2[0]["top_masks"] == [0, 0b110]
     assert r2[1]["logsumexp"] == pytest.approx(np.log(4.0))
+
+
+# ---- regression coefficients (beta_all)
+
+@pytest.mark.parametrize("m,n,seed", [(1, 9, 1), (4, 12, 2), (6, 40, 3), (8, 120, 4)])
+def test_beta_all_matches_lstsq(m, n, seed):
+    """Every family's coefficients against numpy's least squares, whole tables at m <= 8;
+    zeros outside the parent set; and the residual they leave is the oracle's RSS."""
+    X = linear_gaussian(m, n, 0.4, 0.5, 1.5, seed=seed)
+    B = oracle.beta_all(X, threads=3)
+    rss = oracle.score_all(X, oracle.OUT_RSS, threads=2)
+    for c, S in _families(m):
+        i = oracle.family_index(m, c, _mask(S))
+        want = np.zeros(m)
+        if S:
+            want[list(S)] = np.linalg.lstsq(X[:, list(S)], X[:, c], rcond=None)[0]
+        assert np.allclose(B[i], want, rtol=1e-10, atol=1e-12 * max(1.0, np.abs(want).max()))
+        r = X[:, c] - X @ B[i]
+        assert float(r @ r) == pytest.approx(rss[i], rel=1e-10)
