@@ -364,12 +364,13 @@ def test_column_vif(gs, name):
     assert np.abs(vif / want2 - 1).max() <= 1e-9
 
 
-# FP32 walk precision envelope (relative RSS error against the FP64 oracle), fitted to
-# measurements of segments of L Givens steps on data of largest VIF V:
+# FP32 walk precision envelope (relative RSS error against the FP64 oracle), fitted with
+# a margin of at least 1.3 to measurements of segments of L Givens steps on data of
+# largest VIF V (collinearity sweeps at m = 12 and 14, the m = 20 and m = 26 workloads):
 #   E(L, V) = u (A sqrt(L) + sqrt(V) (B0 + B1 sqrt(L))),  u = 2^-24,
-# with A = 6, B0 = 2.5, B1 = 0.12.  1e-4 then holds at the default segment length
-# (L = 8178) for V <= 7.3e3.
-ENV_A, ENV_B0, ENV_B1 = 6.0, 2.5, 0.12
+# with A = 6, B0 = 2.5, B1 = 0.2.  1e-4 then holds at the default segment length
+# (L = 8178) for V <= 3.0e3, at L = 120 for V <= 1.2e5.
+ENV_A, ENV_B0, ENV_B1 = 6.0, 2.5, 0.2
 
 
 def fp32_envelope(L, V):
