@@ -15,6 +15,9 @@ Prints one JSON line.  Besides the contract fields it carries
                 switched off);
   fp64_walk     the same step with the walk in FP64 (families/s);
   fp32_vs_fp64  max relative RSS difference of the two walks over the whole table;
+  concurrent    the same step for several independent datasets of the same shape in
+                flight at once, one plan and one stream each (a serving loop's
+                throughput; every table is checked bit-identical to a one-at-a-time call);
   batched       256 bootstrap datasets (m 12..18, n 200..2000) in one graph replay of
                 gs_score_batched, with the autotuned cap on k, against 256 sequential
                 gs_score_all calls with the same plans;
@@ -195,6 +198,56 @@ def bench_batched(steps: int, stream):
             "walk_waves_per_simd": 4}
 
 
+def bench_concurrent(m: int, n: int, cfg, steps: int, nstreams: int, ref_out, X0):
+    """steps datasets of the workload's shape, round-robin over nstreams streams (one
+    plan and one output table each); the families/s of the whole job."""
+    import torch
+
+    import paper_1901_07643_amd as gs
+    from datagen import linear_gaussian
+    dev = X0.device
+    nfam = gs.num_families(m)
+    Xs = [X0] + [torch.as_tensor(linear_gaussian(m, n, cfg.p_edge, cfg.lo, cfg.hi,
+                                                 seed=cfg.seed + 1000 + i), device=dev)
+                 for i in range(1, nstreams)]
+    plans = [gs.Plan(m) for _ in range(nstreams)]
+    outs = [torch.empty(nfam, dtype=torch.float32, device=dev) for _ in range(nstreams)]
+    streams = [torch.cuda.Stream(dev) for _ in range(nstreams)]
+
+    def run(count):
+        for i in range(count):
+            j = i % nstreams
+            with torch.cuda.stream(streams[j]):
+                gs.score_all(Xs[j], plan=plans[j], out=outs[j], check_status=False)
+
+    run(2 * nstreams)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(streams[0])
+    for st in streams[1:]:
+        st.wait_event(e0)
+    run(steps)
+    for st in streams[1:]:
+        ev = torch.cuda.Event()
+        ev.record(st)
+        streams[0].wait_event(ev)
+    e1.record(streams[0])
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    for p in plans:
+        if p.status() != gs.GS_OK:
+            raise SystemExit(f"device status {p.status()}: {gs.last_error()}")
+    identical = bool(torch.equal(outs[0], ref_out))
+    for p in plans:
+        p.close()
+    del outs
+    torch.cuda.synchronize()
+    return {"datasets_in_flight": nstreams, "datasets": steps, "ms_per_dataset": ms,
+            "value": nfam / (ms * 1e-3), "unit": "families/s",
+            "table_identical_to_single_call": identical}
+
+
 def bench_reduce(X, plan, steps: int, stream):
     """The fused consumer gs_score_reduce on the same workload: per child the minimum BIC
     and its parent set and ln sum exp(-BIC) (and the 8 best parent sets), with no table
@@ -267,6 +320,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--no-reduce", action="store_true", help="skip the fused reduction")
+    ap.add_argument("--concurrent", type=int, default=3,
+                    help="datasets in flight for the concurrent measurement (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (counter calibration)")
     args = ap.parse_args()
@@ -365,6 +420,12 @@ def main():
         "stages_ms": {"r0_qr": stage_ms[0], "anchors": stage_ms[1], "walk": stage_ms[2],
                       "call": stage_ms[3]},
     }
+
+    if args.concurrent > 1:
+        res["concurrent"] = bench_concurrent(m, n, cfg, args.steps, args.concurrent, out, X)
+        print(f"# {args.concurrent} datasets in flight: "
+              f"{res['concurrent']['ms_per_dataset']:.4f} ms per dataset", file=sys.stderr,
+              flush=True)
 
     if not args.no_fp64:
         out64 = torch.empty(nfam, dtype=torch.float64, device=dev)
