@@ -36,8 +36,9 @@ struct gs_batch_s {
     std::vector<TsqrJob> jobs;  // all passes, concatenated
     std::vector<int> pass_off, pass_cnt;
     std::vector<int> pass0_job_item;  // for pass-0 jobs: dataset index (A = X of it)
-    std::vector<size_t> prog_off, lane_off, r0_off, qr_off, qr_len, an_off, tl_off;
-    size_t prog_total = 0, lane_total = 0, r0_total = 0, qr_total = 0, an_total = 0, tl_total = 0;
+    std::vector<size_t> prog_off, lane_off, r0_off, qr_off, qr_len, an_off, tl_off, eb_off;
+    size_t prog_total = 0, lane_total = 0, r0_total = 0, qr_total = 0, an_total = 0, tl_total = 0,
+           eb_total = 0;
 
     // device
     int device = -1;
@@ -47,6 +48,7 @@ struct gs_batch_s {
     double *d_r0 = nullptr, *d_qr = nullptr;
     float *d_anchor = nullptr, *d_tail = nullptr;
     int *d_status = nullptr;
+    int *d_eblk = nullptr;  // first-pass block exponents of every dataset
     ColStats *d_stats = nullptr;
     BatchItem *d_items = nullptr;
     int64_t *d_seg_prefix = nullptr;
@@ -79,9 +81,9 @@ void batch_free_device(gs_batch_s *b) {
     if (b->done) (void)hipEventDestroy(b->done);
     b->cap = nullptr;
     b->done = nullptr;
-    void *ptrs[] = {b->d_prog, b->d_lane_seg, b->d_lane_loc, b->d_r0, b->d_qr, b->d_anchor,
-                    b->d_tail, b->d_status, b->d_stats, b->d_items, b->d_seg_prefix, b->d_wave_item,
-                    b->d_wave_local, b->d_jobs};
+    void *ptrs[] = {b->d_prog,   b->d_lane_seg, b->d_lane_loc,   b->d_r0,        b->d_qr,
+                    b->d_anchor, b->d_tail,     b->d_status,     b->d_eblk,      b->d_stats,
+                    b->d_items,  b->d_seg_prefix, b->d_wave_item, b->d_wave_local, b->d_jobs};
     for (void *p : ptrs) (void)hipFree(p);
     b->d_prog = nullptr;
     b->d_lane_seg = nullptr;
@@ -89,6 +91,7 @@ void batch_free_device(gs_batch_s *b) {
     b->d_r0 = b->d_qr = nullptr;
     b->d_anchor = b->d_tail = nullptr;
     b->d_status = nullptr;
+    b->d_eblk = nullptr;
     b->d_stats = nullptr;
     b->d_items = nullptr;
     b->d_seg_prefix = nullptr;
@@ -133,6 +136,7 @@ int batch_ensure_device(gs_batch_s *b) {
         (e = hipMalloc(&b->d_anchor, b->an_total * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&b->d_tail, b->tl_total * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&b->d_status, b->count * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&b->d_eblk, std::max<size_t>(b->eb_total, 1) * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&b->d_stats, b->count * sizeof(ColStats))) != hipSuccess ||
         (e = hipMalloc(&b->d_items, 2 * size_t(b->count) * sizeof(BatchItem))) != hipSuccess ||
         (e = alloc_copy(&b->d_seg_prefix, b->seg_prefix.data(), b->seg_prefix.size() * 8)) !=
@@ -169,6 +173,7 @@ int batch_ensure_device(gs_batch_s *b) {
         const int it = int(reinterpret_cast<intptr_t>(jb.status));  // dataset index, see create
         jb.status = b->d_status + it;
         jb.stats = b->d_stats + it;
+        jb.eblk = b->d_eblk + b->eb_off[it];
         const intptr_t rtag = reinterpret_cast<intptr_t>(jb.Rout);
         const intptr_t atag = reinterpret_cast<intptr_t>(jb.A);
         // tags: Rout = -1 -> R0; otherwise offset+1 into d_qr; A = 0 -> X, else offset+1 into d_qr
@@ -213,6 +218,7 @@ int gs_batch_create(int count, const int *m, const int64_t *n, const int *k, gs_
     b->qr_len.resize(count);
     b->an_off.resize(count);
     b->tl_off.resize(count);
+    b->eb_off.resize(count);
     b->seg_prefix.assign(count + 1, 0);
     for (int i = 0; i < count; ++i) {
         const gs_plan_s *p = b->plans[i];
@@ -226,6 +232,8 @@ int gs_batch_create(int count, const int *m, const int64_t *n, const int *k, gs_
         b->qr_off[i] = b->qr_total;
         b->qr_len[i] = size_t(nb0) * p->m * p->m;
         b->qr_total += 2 * b->qr_len[i];
+        b->eb_off[i] = b->eb_total;
+        b->eb_total += size_t(nb0) * 32;
         b->an_off[i] = b->an_total;
         b->an_total += size_t(p->nseg) * p->k * 32;
         b->tl_off[i] = b->tl_total;
@@ -284,10 +292,12 @@ int gs_batch_create(int count, const int *m, const int64_t *n, const int *k, gs_
                                      : reinterpret_cast<double *>(dst + blk * mi * mi);
                 jb.status = reinterpret_cast<int *>(intptr_t(i));
                 jb.stats = nullptr;
+                jb.eblk = nullptr;
                 jb.n_orig = n[i];
                 jb.m = mi;
                 jb.block = int(blk);
                 jb.first = pass == 0;
+                jb.rescale = pass == 1;
                 jb.final_pass = final_pass;
                 b->jobs.push_back(jb);
                 b->pass0_job_item.push_back(pass == 0 ? i : -1);
@@ -342,8 +352,6 @@ static hipError_t enqueue_batch(gs_batch_s *b, bool bic, hipStream_t s) {
     const BatchItem *items = b->d_items + (bic ? 0 : b->count);
     hipError_t e = launch_front_reset(b->d_status, b->d_stats, b->count, s);
     if (e != hipSuccess) return e;
-    if ((e = launch_colmax_batched(b->d_jobs + b->pass_off[0], b->pass_cnt[0], s)) != hipSuccess)
-        return e;
     for (size_t p = 0; p < b->pass_off.size(); ++p)
         if ((e = launch_tsqr_batched(b->d_jobs + b->pass_off[p], b->pass_cnt[p], b->mmax, s)) != hipSuccess)
             return e;

@@ -141,7 +141,9 @@ struct TsqrJob {
     int64_t n_orig;
     int m;
     int block;
-    int first;  // pass 0: reads X and applies the pre-scaling
+    int first;    // pass 0: reads X, scales each column of the block by its own power of two
+    int rescale;  // pass 1: brings the pass-0 blocks to the common scale
+    int *eblk;    // the dataset's pass-0 block exponents (32 ints per block)
     int final_pass;
 };
 
@@ -174,8 +176,6 @@ hipError_t launch_front_reset(int *status, ColStats *stats, int count, hipStream
 int64_t qr_workspace_elems(int64_t n, int m);
 int tsqr_rows_per_block();
 hipError_t launch_tsqr_batched(const TsqrJob *jobs, int njobs, int mmax, hipStream_t s);
-// Column maxima of the data of every pass-0 job (one 128-row block per workgroup).
-hipError_t launch_colmax_batched(const TsqrJob *jobs, int njobs, hipStream_t s);
 
 // Host planner: pack segments into 64-lane waves (plan.cpp).
 int pack_waves(gs_plan_s *p);

@@ -4,12 +4,15 @@
 // O(2 n m^2) step of Sec. 1.1.  Here it is a tall-skinny QR: every workgroup
 // triangularises a block of 128 rows by Householder reflections and writes its
 // m x m R; the stacked R blocks are triangularised again by the same code until one
-// block is left.  Before the first pass a column-maximum pass flags non-finite input
-// and finds, per column, the power of two that brings its largest magnitude into
-// [1/2, 1); the first pass applies it, so that no square or sum of squares of the QR
-// leaves the double range whatever the units of X.  The last pass makes the diagonal
-// non-negative, derives the column statistics the later stages use (the walk's
-// power-of-two equilibration, variance inflation factors) and checks the rank.
+// block is left.  The first pass flags non-finite input and scales each column of its
+// block by the power of two that brings the block's largest magnitude into [1/2, 1),
+// so that no square or sum of squares of the QR leaves the double range whatever the
+// units of X; it records those exponents and raises the column's global exponent
+// exp0 to the largest of them.  The next pass brings every block's R to the common
+// scale 2^-exp0 by exact powers of two (the same numbers as a pre-scaling of all of X
+// by 2^-exp0 would give).  The last pass makes the diagonal non-negative, derives the
+// column statistics the later stages use (the walk's power-of-two equilibration,
+// variance inflation factors) and checks the rank.
 //
 // Layout inside a workgroup (256 threads = 8 row groups x 32 columns): thread
 // (g, c) keeps column c of the rows i = g + 8 r, r = 0..15, in registers.  The
@@ -60,8 +63,9 @@ __device__ __forceinline__ double shfl_half(double v, int src) {
 // GS_GUARD_VIF; below that every pivot pair of the equilibrated walk is far from
 // zero and from the FP32 underflow threshold.
 template <int MM>
-__device__ __forceinline__ void col_stats(double (*Rl)[QR_MMAX + 1], int m, int64_t n,
-                                          int *__restrict__ status, ColStats *__restrict__ st) {
+__device__ __forceinline__ void col_stats(double (*Rl)[QR_MMAX + 1], const int *exps, int m,
+                                          int64_t n, int *__restrict__ status,
+                                          ColStats *__restrict__ st) {
     __shared__ double scl[QR_MMAX];
     __shared__ double Zl[QR_MMAX][QR_MMAX + 1];
     const int c = threadIdx.x;  // 0..31
@@ -77,7 +81,7 @@ __device__ __forceinline__ void col_stats(double (*Rl)[QR_MMAX + 1], int m, int6
             sc = ldexp(1.0, -e);
             ns = ldexp(sqrt(t), -e);
         }
-        const int e0 = st->exp0[c];
+        const int e0 = exps[c];
         st->exp2[c] = (e0 == INT_MIN ? 0 : e0) + e;
         st->scale[c] = sc;
     }
@@ -123,53 +127,6 @@ __device__ __forceinline__ void col_stats(double (*Rl)[QR_MMAX + 1], int m, int6
     }
 }
 
-// Column maxima of one 128-row block of X: flags non-finite entries and raises
-// exp0[c] to the exponent e of the block's largest |x_ic| (|x| = f 2^e, f in [1/2, 1)).
-__device__ __forceinline__ void colmax_block(const double *__restrict__ A, int64_t nrows, int m,
-                                             int64_t lda, int64_t r0, int *__restrict__ status,
-                                             int *__restrict__ exp0) {
-    __shared__ double red[QR_G][QR_MMAX];
-    const int tid = threadIdx.x, c = tid & 31, g = tid >> 5;
-    const int rows = int(min<int64_t>(QR_BR, nrows - r0));
-    double mx = 0.0;
-    int bad = 0;
-#pragma unroll
-    for (int r = 0; r < QR_RPT; ++r) {
-        const int i = g + QR_G * r;
-        if (i < rows && c < m) {
-            const double v = A[(r0 + i) * lda + c];
-            if (!isfinite(v)) bad = 1;
-            mx = fmax(mx, fabs(v));  // fmax ignores a NaN operand
-        }
-    }
-    if (bad) atomicOr(status, GS_FLAG_NOTFINITE);
-    red[g][c] = mx;
-    __syncthreads();
-    if (g == 0 && c < m) {
-        for (int gg = 1; gg < QR_G; ++gg) mx = fmax(mx, red[gg][c]);
-        if (mx > 0.0 && mx <= 1.7976931348623157e308) {
-            int e = 0;
-            (void)frexp(mx, &e);
-            atomicMax(exp0 + c, e);
-        }
-    }
-}
-
-__global__ __launch_bounds__(QR_THREADS) void colmax_kernel(const double *__restrict__ A,
-                                                            int64_t nrows, int m, int64_t lda,
-                                                            int *__restrict__ status,
-                                                            ColStats *__restrict__ stats) {
-    colmax_block(A, nrows, m, lda, int64_t(blockIdx.x) * QR_BR, status, stats->exp0);
-}
-
-__global__ __launch_bounds__(QR_THREADS) void colmax_batched_kernel(const TsqrJob *__restrict__ jobs,
-                                                                    int njobs) {
-    if (int(blockIdx.x) >= njobs) return;
-    const TsqrJob jb = jobs[blockIdx.x];
-    colmax_block(jb.A, jb.nrows, jb.m, jb.lda, int64_t(jb.block) * QR_BR, jb.status,
-                 jb.stats->exp0);
-}
-
 __global__ void front_reset_kernel(int *__restrict__ status, ColStats *__restrict__ stats,
                                    int count) {
     for (int i = int(blockIdx.x * blockDim.x + threadIdx.x); i < count * 32;
@@ -180,35 +137,70 @@ __global__ void front_reset_kernel(int *__restrict__ status, ColStats *__restric
 }
 
 // One 128-row block: A (nrows x m, row stride lda) rows [r0, r0 + 128) -> Rout (m x m).
-// The first pass (first != 0) reads X and applies the pre-scaling 2^-exp0.
+// The first pass (first != 0) reads X: it checks every entry, scales column c of the
+// block by 2^-e (e: the exponent of the block's largest |x_ic|, or INT_MIN for an
+// all-zero column), stores e at eblk[block][c] and raises stats->exp0[c] to it.  The
+// pass after it (rescale != 0) reads those blocks' R factors, row i of A belonging to
+// block i / m, and multiplies each column by 2^(e - exp0).
 template <int MM>
 __device__ __forceinline__ void tsqr_block(const double *__restrict__ A, int64_t nrows, int m,
-                                           int64_t lda, int64_t r0, double *__restrict__ Rout,
-                                           double *__restrict__ Rtrue, int *__restrict__ status,
-                                           ColStats *__restrict__ stats, int first,
+                                           int64_t lda, int64_t r0, int block,
+                                           double *__restrict__ Rout, double *__restrict__ Rtrue,
+                                           int *__restrict__ status, ColStats *__restrict__ stats,
+                                           int first, int rescale, int *__restrict__ eblk,
                                            int final_pass, int64_t n_orig) {
     // per column parity: partial dot products of the 8 row groups, row j, pivot entry
     __shared__ double red[2][QR_G][QR_MMAX];
     __shared__ double rowj[2][QR_MMAX];
     __shared__ double diag[QR_MMAX];
+    __shared__ int exps[QR_MMAX];  // the exponents of the common scale (final pass)
     const int tid = threadIdx.x;
     const int c = tid & 31;   // column
     const int g = tid >> 5;   // row group
     const int rows = int(min<int64_t>(QR_BR, nrows - r0));
 
-    int e0 = 0;
-    if (first && c < m) {
-        const int e = stats->exp0[c];
-        e0 = e == INT_MIN ? 0 : e;  // INT_MIN: an all-zero (or non-finite) column
-    }
     double x[QR_RPT];
 #pragma unroll
     for (int r = 0; r < QR_RPT; ++r) {
         const int i = g + QR_G * r;
-        double v = 0.0;
-        if (i < rows && c < m) v = A[(r0 + i) * lda + c];
-        x[r] = first ? ldexp(v, -e0) : v;
+        x[r] = (i < rows && c < m) ? A[(r0 + i) * lda + c] : 0.0;
     }
+    if (first) {
+        double mx = 0.0;
+        int bad = 0;
+#pragma unroll
+        for (int r = 0; r < QR_RPT; ++r) {
+            if (!isfinite(x[r])) bad = 1;
+            mx = fmax(mx, fabs(x[r]));  // fmax ignores a NaN operand
+        }
+        if (bad) atomicOr(status, GS_FLAG_NOTFINITE);
+        red[0][g][c] = mx;
+        __syncthreads();
+#pragma unroll
+        for (int gg = 0; gg < QR_G; ++gg) mx = fmax(mx, red[0][gg][c]);
+        int e = INT_MIN;
+        if (mx > 0.0 && mx <= 1.7976931348623157e308) (void)frexp(mx, &e);
+        if (g == 0 && c < m) {
+            if (e != INT_MIN) atomicMax(stats->exp0 + c, e);
+            if (final_pass) exps[c] = e;
+            else eblk[block * 32 + c] = e;
+        }
+        const int sh = e == INT_MIN ? 0 : -e;
+#pragma unroll
+        for (int r = 0; r < QR_RPT; ++r) x[r] = ldexp(x[r], sh);
+        __syncthreads();  // the maxima are read before the QR reuses red
+    } else if (rescale && c < m) {
+        const int E = stats->exp0[c];
+#pragma unroll
+        for (int r = 0; r < QR_RPT; ++r) {
+            const int i = g + QR_G * r;
+            if (i < rows) {
+                const int e = eblk[int((r0 + i) / m) * 32 + c];
+                x[r] = e == INT_MIN ? 0.0 : ldexp(x[r], e - E);
+            }
+        }
+    }
+    if (final_pass && !first && g == 0 && c < m) exps[c] = stats->exp0[c];
 
     // Rows past the block's end hold zeros; a column j >= rows then has a zero
     // tail and its step leaves every row unchanged (normx2 = a^2 with a = 0 below the
@@ -285,27 +277,23 @@ __device__ __forceinline__ void tsqr_block(const double *__restrict__ A, int64_t
             Rout[i * m + c] = val;
             Rl[i][c] = val;
             if (Rtrue) {
-                const int e = stats->exp0[c];
+                const int e = exps[c];
                 Rtrue[i * m + c] = ldexp(val, e == INT_MIN ? 0 : e);
             }
         }
     }
     __syncthreads();
-    if (tid < 32) col_stats<MM>(Rl, m, n_orig, status, stats);
+    if (tid < 32) col_stats<MM>(Rl, exps, m, n_orig, status, stats);
 }
 
 template <int MM>
-__global__ __launch_bounds__(QR_THREADS) void tsqr_block_kernel(const double *__restrict__ A,
-                                                                int64_t nrows, int m, int64_t lda,
-                                                                double *__restrict__ Rout,
-                                                                double *__restrict__ Rtrue,
-                                                                int *__restrict__ status,
-                                                                ColStats *__restrict__ stats,
-                                                                int first, int final_pass,
-                                                                int64_t n_orig) {
-    tsqr_block<MM>(A, nrows, m, lda, int64_t(blockIdx.x) * QR_BR,
-                   Rout + int64_t(blockIdx.x) * m * m, Rtrue, status, stats, first, final_pass,
-                   n_orig);
+__global__ __launch_bounds__(QR_THREADS) void tsqr_block_kernel(
+    const double *__restrict__ A, int64_t nrows, int m, int64_t lda, double *__restrict__ Rout,
+    double *__restrict__ Rtrue, int *__restrict__ status, ColStats *__restrict__ stats, int first,
+    int rescale, int *__restrict__ eblk, int final_pass, int64_t n_orig) {
+    tsqr_block<MM>(A, nrows, m, lda, int64_t(blockIdx.x) * QR_BR, int(blockIdx.x),
+                   Rout + int64_t(blockIdx.x) * m * m, Rtrue, status, stats, first, rescale, eblk,
+                   final_pass, n_orig);
 }
 
 // Batched passes: one job per workgroup (see TsqrJob); MM covers the largest m.
@@ -314,13 +302,16 @@ __global__ __launch_bounds__(QR_THREADS) void tsqr_batched_kernel(const TsqrJob 
                                                                   int njobs) {
     if (int(blockIdx.x) >= njobs) return;
     const TsqrJob jb = jobs[blockIdx.x];
-    tsqr_block<MM>(jb.A, jb.nrows, jb.m, jb.lda, int64_t(jb.block) * QR_BR, jb.Rout, nullptr,
-                   jb.status, jb.stats, jb.first, jb.final_pass, jb.n_orig);
+    tsqr_block<MM>(jb.A, jb.nrows, jb.m, jb.lda, int64_t(jb.block) * QR_BR, jb.block, jb.Rout,
+                   nullptr, jb.status, jb.stats, jb.first, jb.rescale, jb.eblk, jb.final_pass,
+                   jb.n_orig);
 }
 
+// Per buffer: the R blocks of the first pass, then (first buffer only) their column
+// exponents, 32 ints per block.
 int64_t qr_workspace_elems(int64_t n, int m) {
     const int64_t nb = (n + QR_BR - 1) / QR_BR;
-    return nb * int64_t(m) * m + int64_t(m) * m;
+    return nb * int64_t(m) * m + int64_t(m) * m + 16 * nb;
 }
 
 int tsqr_rows_per_block() { return QR_BR; }
@@ -340,11 +331,13 @@ int tsqr_rows_per_block() { return QR_BR; }
 
 static hipError_t launch_block(const double *A, int64_t rows, int m, int64_t lda, double *Rout,
                                double *Rtrue, int *status, ColStats *stats, int first,
-                               int final_pass, int64_t n, int64_t nb, hipStream_t s) {
+                               int rescale, int *eblk, int final_pass, int64_t n, int64_t nb,
+                               hipStream_t s) {
 #define GS_QR_CASE(MMV)                                                                        \
     case MMV:                                                                                  \
         hipLaunchKernelGGL((tsqr_block_kernel<MMV>), dim3(unsigned(nb)), dim3(QR_THREADS), 0, s, \
-                           A, rows, m, lda, Rout, Rtrue, status, stats, first, final_pass, n); \
+                           A, rows, m, lda, Rout, Rtrue, status, stats, first, rescale, eblk,  \
+                           final_pass, n);                                                     \
         break;
     GS_QR_SWITCH((m + 3) / 4 * 4, GS_QR_CASE)
 #undef GS_QR_CASE
@@ -358,32 +351,24 @@ hipError_t launch_front_reset(int *status, ColStats *stats, int count, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_colmax_batched(const TsqrJob *jobs, int njobs, hipStream_t s) {
-    hipLaunchKernelGGL(colmax_batched_kernel, dim3(unsigned(njobs)), dim3(QR_THREADS), 0, s, jobs,
-                       njobs);
-    return hipGetLastError();
-}
-
 hipError_t launch_qr_r0(const double *X, int64_t n, int m, int64_t ldx, double *R0, double *Rtrue,
                         double *bufA, double *bufB, int *status, ColStats *stats, hipStream_t s) {
-    {
-        const int64_t nb = (n + QR_BR - 1) / QR_BR;
-        hipLaunchKernelGGL(colmax_kernel, dim3(unsigned(nb)), dim3(QR_THREADS), 0, s, X, n, m, ldx,
-                           status, stats);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    const int64_t nb0 = (n + QR_BR - 1) / QR_BR;
+    // the first pass's block exponents, behind the largest R stack in bufA
+    int *eblk = reinterpret_cast<int *>(bufA + nb0 * int64_t(m) * m + int64_t(m) * m);
     const double *src = X;
     int64_t rows = n, lda = ldx;
     double *dst = bufA, *other = bufB;
-    int first = 1;
+    int first = 1, rescale = 0;
     for (;;) {
         const int64_t nb = (rows + QR_BR - 1) / QR_BR;
         if (nb == 1)
-            return launch_block(src, rows, m, lda, R0, Rtrue, status, stats, first, 1, n, 1, s);
-        hipError_t e =
-            launch_block(src, rows, m, lda, dst, nullptr, status, stats, first, 0, n, nb, s);
+            return launch_block(src, rows, m, lda, R0, Rtrue, status, stats, first, rescale, eblk,
+                                1, n, 1, s);
+        hipError_t e = launch_block(src, rows, m, lda, dst, nullptr, status, stats, first, rescale,
+                                    eblk, 0, n, nb, s);
         if (e != hipSuccess) return e;
+        rescale = first;
         first = 0;
         src = dst;
         rows = nb * m;

@@ -331,6 +331,33 @@ def test_full_double_range(gs, e):
         _expect_status(gs, Xa, "rss", "fp64", gs.GS_ERANGE)
 
 
+@pytest.mark.parametrize("n", [700, 20000])
+def test_row_blocks_at_different_scales(gs, n):
+    """Column c of the 128-row block b of X scaled by 2^s_bc, s_bc in [-20, 20]: the
+    first QR pass scales every block by its own powers of two and the next pass brings
+    the blocks to one scale, exactly.  R0 of X and of X 2^t (t an integer per column)
+    must then differ by exactly the factors 2^t, R0^T R0 must equal X^T X to rounding,
+    and the FP64 table must match the oracle.  (n = 20000 takes three passes, so the
+    rescaling pass is not the last one.)"""
+    m = 6
+    X = linear_gaussian(m, n, 0.3, 0.5, 1.5, seed=n)
+    rng = np.random.default_rng(n)
+    nb = (n + 127) // 128
+    s = rng.integers(-20, 21, size=(nb, m))
+    Xs = np.ldexp(X, np.repeat(s, 128, axis=0)[:n])
+    t = rng.integers(-300, 301, size=m)
+    R = gs.qr_r0(torch.as_tensor(Xs, device="cuda")).cpu().numpy()
+    Rt = gs.qr_r0(torch.as_tensor(np.ldexp(Xs, t[None, :]), device="cuda")).cpu().numpy()
+    assert np.array_equal(np.ldexp(R, t[None, :]), Rt)
+    G = Xs.T @ Xs
+    d = np.sqrt(np.diag(G))
+    assert (np.abs(R.T @ R - G) / np.outer(d, d)).max() <= 1e-12
+    ref = oracle.score_all(Xs, oracle.OUT_RSS)
+    got = _run(gs, Xs, "rss", "fp64").cpu().numpy()
+    err = _assert_rss(got, ref, TOL["fp64"], f"block scales n={n} fp64")
+    print(f"\nrow blocks at 2^[-20, 20], n={n}: FP64 max rel RSS err {err:.3e}")
+
+
 def test_tiny_column_is_not_rank_deficient(gs):
     """One column in units 1e-13 smaller than the others: well posed (the rank test is
     scale free), both walks within their tolerances."""
