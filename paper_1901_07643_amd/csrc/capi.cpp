@@ -49,6 +49,7 @@ void free_device(gs_plan_s *p) {
     (void)hipFree(p->red.psum);
     (void)hipFree(p->red.ptopv);
     (void)hipFree(p->red.ptopm);
+    (void)hipFree(p->red.stage);
     p->red = ReducePartials{};
     p->d_anchorbar = p->d_tailbar = p->d_vout = p->d_partial = p->d_B = p->d_K = nullptr;
     p->d_prog = nullptr;
@@ -348,11 +349,14 @@ int gs_score_reduce(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx
             (e = hipMalloc(&p->red.pmask, cnt * 4)) != hipSuccess ||
             (e = hipMalloc(&p->red.psum, cnt * 4)) != hipSuccess ||
             (e = hipMalloc(&p->red.ptopv, cnt * GS_REDUCE_TOPK * 4)) != hipSuccess ||
-            (e = hipMalloc(&p->red.ptopm, cnt * GS_REDUCE_TOPK * 4)) != hipSuccess) {
+            (e = hipMalloc(&p->red.ptopm, cnt * GS_REDUCE_TOPK * 4)) != hipSuccess ||
+            (e = hipMalloc(&p->red.stage, size_t(p->m) * GS_REDUCE_SPLIT * sizeof(ReduceStage))) !=
+                hipSuccess) {
             (void)hipFree(p->red.pmin);
             (void)hipFree(p->red.pmask);
             (void)hipFree(p->red.psum);
             (void)hipFree(p->red.ptopv);
+            (void)hipFree(p->red.ptopm);
             p->red = ReducePartials{};
             return fail(GS_ENOMEM, std::string("reduction workspace: ") + hipGetErrorString(e));
         }

@@ -40,12 +40,23 @@ constexpr double GS_GUARD_VIF = 1e8;
 // segment): the minimum BIC, its parent set, the sum of exp(min - BIC) over the
 // segment's parent sets, and (top-k mode) the GS_REDUCE_TOPK smallest values, ascending.
 #define GS_REDUCE_TOPK 8
+// The child merge runs in two launches: up to GS_REDUCE_SPLIT workgroups per child
+// reduce fixed slices of the segments into a ReduceStage each, then one wave per
+// child merges those in order.
+#define GS_REDUCE_SPLIT 32
+struct ReduceStage {
+    double mn, sum;
+    uint32_t mask;
+    float tv[GS_REDUCE_TOPK];
+    uint32_t tm[GS_REDUCE_TOPK];
+};
 struct ReducePartials {
     float *pmin = nullptr;
     uint32_t *pmask = nullptr;
     float *psum = nullptr;
     float *ptopv = nullptr;
     uint32_t *ptopm = nullptr;
+    ReduceStage *stage = nullptr;  // m x GS_REDUCE_SPLIT
 };
 
 struct gs_plan_s {
