@@ -15,9 +15,9 @@ Prints one JSON line.  Besides the contract fields it carries
                 switched off);
   fp64_walk     the same step with the walk in FP64 (families/s);
   fp32_vs_fp64  max relative RSS difference of the two walks over the whole table;
-  concurrent    the same step for several independent datasets of the same shape in
-                flight at once, one plan and one stream each (a serving loop's
-                throughput; every table is checked bit-identical to a one-at-a-time call);
+  concurrent    the same step for a list of independent datasets of the same shape
+                through gs_score_all_many, three in flight at once (a serving loop's
+                throughput; the first table is checked bit-identical to a single call);
   batched       256 bootstrap datasets (m 12..18, n 200..2000) in one graph replay of
                 gs_score_batched, with the autotuned cap on k, against 256 sequential
                 gs_score_all calls with the same plans;
@@ -198,9 +198,10 @@ def bench_batched(steps: int, stream):
             "walk_waves_per_simd": 4}
 
 
-def bench_concurrent(m: int, n: int, cfg, steps: int, nstreams: int, ref_out, X0):
-    """steps datasets of the workload's shape, round-robin over nstreams streams (one
-    plan and one output table each); the families/s of the whole job."""
+def bench_concurrent(m: int, n: int, cfg, steps: int, in_flight: int, ref_out, X0, stream):
+    """steps datasets of the workload's shape through gs_score_all_many with in_flight
+    of them in progress at once (in_flight distinct datasets, cycled; each slot keeps
+    its own table); the families/s of the whole job."""
     import torch
 
     import paper_1901_07643_amd as gs
@@ -209,42 +210,23 @@ def bench_concurrent(m: int, n: int, cfg, steps: int, nstreams: int, ref_out, X0
     nfam = gs.num_families(m)
     Xs = [X0] + [torch.as_tensor(linear_gaussian(m, n, cfg.p_edge, cfg.lo, cfg.hi,
                                                  seed=cfg.seed + 1000 + i), device=dev)
-                 for i in range(1, nstreams)]
-    plans = [gs.Plan(m) for _ in range(nstreams)]
-    outs = [torch.empty(nfam, dtype=torch.float32, device=dev) for _ in range(nstreams)]
-    streams = [torch.cuda.Stream(dev) for _ in range(nstreams)]
-
-    def run(count):
-        for i in range(count):
-            j = i % nstreams
-            with torch.cuda.stream(streams[j]):
-                gs.score_all(Xs[j], plan=plans[j], out=outs[j], check_status=False)
-
-    run(2 * nstreams)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(streams[0])
-    for st in streams[1:]:
-        st.wait_event(e0)
-    run(steps)
-    for st in streams[1:]:
-        ev = torch.cuda.Event()
-        ev.record(st)
-        streams[0].wait_event(ev)
-    e1.record(streams[0])
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    for p in plans:
-        if p.status() != gs.GS_OK:
-            raise SystemExit(f"device status {p.status()}: {gs.last_error()}")
+                 for i in range(1, in_flight)]
+    outs = [torch.empty(nfam, dtype=torch.float32, device=dev) for _ in range(in_flight)]
+    plan = gs.Plan(m)
+    Xl = [Xs[i % in_flight] for i in range(steps)]
+    Ol = [outs[i % in_flight] for i in range(steps)]
+    gs.score_all_many(Xl[:2 * in_flight], plan=plan, outs=Ol[:2 * in_flight], in_flight=in_flight)
+    ms = _event_ms(lambda: gs.score_all_many(Xl, plan=plan, outs=Ol, in_flight=in_flight,
+                                             check_status=False), 1, stream) / steps
+    if any(st != gs.GS_OK for st in plan.many_status()):
+        raise SystemExit(f"concurrent workload: device status {plan.many_status()}")
     identical = bool(torch.equal(outs[0], ref_out))
-    for p in plans:
-        p.close()
+    plan.close()
     del outs
     torch.cuda.synchronize()
-    return {"datasets_in_flight": nstreams, "datasets": steps, "ms_per_dataset": ms,
+    return {"datasets_in_flight": in_flight, "datasets": steps, "ms_per_dataset": ms,
             "value": nfam / (ms * 1e-3), "unit": "families/s",
+            "entry_point": "gs_score_all_many",
             "table_identical_to_single_call": identical}
 
 
@@ -422,7 +404,8 @@ def main():
     }
 
     if args.concurrent > 1:
-        res["concurrent"] = bench_concurrent(m, n, cfg, args.steps, args.concurrent, out, X)
+        res["concurrent"] = bench_concurrent(m, n, cfg, args.steps, args.concurrent, out, X,
+                                             stream)
         print(f"# {args.concurrent} datasets in flight: "
               f"{res['concurrent']['ms_per_dataset']:.4f} ms per dataset", file=sys.stderr,
               flush=True)

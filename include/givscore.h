@@ -200,6 +200,32 @@ int gs_score_reduce(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t 
 int gs_score_all_static(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
                         float *scores, int what, int *status_code, void *stream);
 
+/* Many datasets of one shape, each scored as by gs_score_all (FP32 walk), with up to
+ * in_flight of them in progress at once.  Every dataset is its own instance of the
+ * problem of Sec. 1; its work splits into independent pieces (Sec. 6), and pieces of
+ * different datasets can run side by side like those of one: here one dataset's R0 and
+ * anchors overlap another's walk, and the walks share the device.  The plan keeps
+ * in_flight - 1 extra workspaces (plans with its m, k and inner block) and in_flight
+ * internal streams, created on the first call that needs them; the streams fork from
+ * `stream` and `stream` waits for all of them before its later work.
+ *   X[i]: device, n x m row-major FP64 (row stride ldx), i = 0..count-1;
+ *   scores[i]: device, m * 2^(m-1) floats, 16-byte aligned (table order of
+ *     gs_family_index); every table is bit-identical to gs_score_all on X[i] alone;
+ *   what: GS_OUT_BIC or GS_OUT_RSS; in_flight: 1..GS_MANY_MAX_IN_FLIGHT.
+ * The arrays X and scores are host arrays of device pointers, read during the call.
+ * gs_many_status gives each dataset's status.  Errors: GS_EINVAL on bad arguments
+ * (before any device work), GS_ENOMEM; an error after some datasets were enqueued
+ * still makes `stream` wait for them. */
+#define GS_MANY_MAX_IN_FLIGHT 8
+int gs_score_all_many(gs_plan_t *plan, int count, const double *const *X, int64_t n,
+                      int64_t ldx, float *const *scores, int what, int in_flight, void *stream);
+
+/* Per-dataset status of the last gs_score_all_many call on this plan: waits for it,
+ * writes count codes (GS_OK, GS_ERANK, GS_ENOTFINITE, GS_ERANGE) to status (host) and
+ * returns the first non-OK code in dataset order (GS_OK if none).  GS_EINVAL if the
+ * plan has not run gs_score_all_many. */
+int gs_many_status(gs_plan_t *plan, int *status);
+
 /* Testing: the FP32 walk of gs_score_all (same plan, same launch, same store path)
  * with every table write replaced by an atomic increment of a 32-bit counter at the
  * same index: counts (device, m * 2^(m-1) uint32, 16-byte aligned, zeroed by the

@@ -23,7 +23,7 @@ from ._abi import (BatchData, ReduceOut, GS_EINVAL, GS_ENOTFINITE, GS_ERANGE, GS
                    GS_OUT_BIC, GS_OUT_RSS, GivScoreError, PlanInfo, check, last_error, lib)
 
 __all__ = [
-    "Plan", "Batch", "score_all", "score_reduce", "score_beta", "count_writes", "score_backward", "givscore", "GivScore", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
+    "Plan", "Batch", "score_all", "score_all_many", "score_reduce", "score_beta", "count_writes", "score_backward", "givscore", "GivScore", "qr_r0", "num_families", "family_index", "upsilon", "GivScoreError",
     "GS_OK", "GS_EINVAL", "GS_ERANK", "GS_ENOTFINITE", "GS_ERANGE", "GS_MAX_M", "lib", "last_error",
 ]
 
@@ -58,6 +58,7 @@ class Plan:
         check(lib().gs_plan_tuned(m, k, ks, ctypes.byref(h)))
         self._h = h
         self.m = m
+        self._many_count = 0
 
     @property
     def handle(self):
@@ -88,6 +89,13 @@ class Plan:
         """Wait for the last call and return its device status code (0, GS_ERANK,
         GS_ENOTFINITE, GS_ERANGE)."""
         return int(lib().gs_sync_status(self.handle))
+
+    def many_status(self) -> list[int]:
+        """Per-dataset status codes of the plan's last score_all_many call (waits)."""
+        cnt = self._many_count
+        st = (ctypes.c_int * max(cnt, 1))()
+        lib().gs_many_status(self.handle, st)
+        return [int(st[i]) for i in range(cnt)]
 
     def vif(self) -> np.ndarray:
         """Variance inflation factors of the columns of the last call's data."""
@@ -172,6 +180,44 @@ def score_all(X, plan: Plan | None = None, what: str = "bic", precision: str = "
         if check_status:
             check(plan.status())
     return out
+
+
+def score_all_many(Xs, plan: Plan | None = None, what: str = "bic", outs=None,
+                   in_flight: int = 3, check_status: bool = True):
+    """FP32 score tables of many datasets of one shape (gs_score_all_many): up to
+    in_flight of them in progress at once on the plan's internal streams, forked from
+    and joined to the current stream.  Xs: list of (n, m) float64 device tensors with
+    the same n, m and row stride.  Returns the list of tables (float32, m * 2^(m-1)),
+    each bit-identical to score_all on its dataset.  With check_status the call waits
+    and raises GivScoreError naming the first dataset whose status is not GS_OK."""
+    import torch
+    if not Xs:
+        raise ValueError("Xs is empty")
+    n, m, ldx = _check_X(Xs[0], plan.m if plan else None)
+    for X in Xs:
+        if _check_X(X, m) != (n, m, ldx) or X.device != Xs[0].device:
+            raise ValueError("every dataset needs the same shape, row stride and device")
+    plan = plan or Plan(m)
+    w = {"bic": GS_OUT_BIC, "rss": GS_OUT_RSS}[what]
+    N = num_families(m)
+    if outs is None:
+        outs = [torch.empty(N, dtype=torch.float32, device=Xs[0].device) for _ in Xs]
+    elif len(outs) != len(Xs) or any(o.dtype != torch.float32 or o.numel() != N or
+                                     not o.is_contiguous() or o.device != Xs[0].device
+                                     for o in outs):
+        raise ValueError("outs must hold one contiguous float32 tensor of m*2^(m-1) "
+                         "elements per dataset")
+    cnt = len(Xs)
+    xp = (ctypes.c_void_p * cnt)(*[X.data_ptr() for X in Xs])
+    op = (ctypes.c_void_p * cnt)(*[o.data_ptr() for o in outs])
+    with torch.cuda.device(Xs[0].device):
+        check(lib().gs_score_all_many(plan.handle, cnt, xp, n, ldx, op, w, in_flight,
+                                      _stream(Xs[0].device)))
+        plan._many_count = cnt
+        if check_status:
+            st = (ctypes.c_int * cnt)()
+            check(lib().gs_many_status(plan.handle, st))
+    return outs
 
 
 def score_reduce(X, plan: Plan | None = None, top_k: int = 0, check_status: bool = True):

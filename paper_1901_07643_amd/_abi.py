@@ -81,6 +81,9 @@ def lib():
         "gs_score_beta": (i32, [vp, vp, i64, i32, i64, vp, vp]),
         "gs_score_reduce": (i32, [vp, vp, i64, i32, i64, ctypes.POINTER(ReduceOut), vp]),
         "gs_score_all_static": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, vp]),
+        "gs_score_all_many": (i32, [vp, i32, ctypes.POINTER(vp), i64, i64, ctypes.POINTER(vp),
+                                    i32, i32, vp]),
+        "gs_many_status": (i32, [vp, ctypes.POINTER(ctypes.c_int)]),
         "gs_score_backward": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
         "gs_score_backward_f64": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
         "gs_sync_status": (i32, [vp]),

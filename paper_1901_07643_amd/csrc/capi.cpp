@@ -288,11 +288,114 @@ void gs_plan_destroy(gs_plan_t *p) {
         int cur = 0;
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(p->device);
+        for (hipEvent_t e : p->slot_join) (void)hipEventSynchronize(e);
         if (p->done) (void)hipEventSynchronize(p->done);
+        for (hipEvent_t e : p->slot_join) (void)hipEventDestroy(e);
+        for (hipStream_t s : p->slot_streams) (void)hipStreamDestroy(s);
+        if (p->fork) (void)hipEventDestroy(p->fork);
+        (void)hipFree(p->d_many_status);
         free_device(p);
         (void)hipSetDevice(cur);
     }
+    for (gs_plan_s *q : p->slots) gs_plan_destroy(q);
     delete p;
+}
+
+int gs_score_all_many(gs_plan_t *p, int count, const double *const *X, int64_t n, int64_t ldx,
+                      float *const *scores, int what, int in_flight, void *stream) {
+    const char *who = "gs_score_all_many";
+    if (!p || !X || !scores) return fail(GS_EINVAL, "gs_score_all_many: NULL argument");
+    if (count < 1) return fail(GS_EINVAL, "gs_score_all_many: count must be positive");
+    if (in_flight < 1 || in_flight > GS_MANY_MAX_IN_FLIGHT)
+        return fail(GS_EINVAL, "gs_score_all_many: in_flight must be in 1..8");
+    if (what != GS_OUT_BIC && what != GS_OUT_RSS)
+        return fail(GS_EINVAL, "gs_score_all_many: what must be GS_OUT_BIC or GS_OUT_RSS");
+    int st;
+    for (int i = 0; i < count; ++i)
+        if ((st = check_common(p, X[i], n, p->m, ldx, scores[i], who)) != GS_OK) return st;
+    in_flight = std::min(in_flight, count);
+    while (int(p->slots.size()) < in_flight - 1) {
+        gs_plan_t *q = nullptr;
+        if ((st = gs_plan_tuned(p->m, p->k, p->ks, &q)) != GS_OK) return st;
+        p->slots.push_back(q);
+    }
+    if ((st = ensure_workspace(p, n)) != GS_OK) return st;
+    hipError_t e;
+    if (!p->fork && (e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "hipEventCreate");
+    while (int(p->slot_streams.size()) < in_flight) {
+        hipStream_t t = nullptr;
+        hipEvent_t j = nullptr;
+        if ((e = hipStreamCreateWithFlags(&t, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreate");
+        if ((e = hipEventCreateWithFlags(&j, hipEventDisableTiming)) != hipSuccess) {
+            (void)hipStreamDestroy(t);
+            return hip_fail(e, "hipEventCreate");
+        }
+        p->slot_streams.push_back(t);
+        p->slot_join.push_back(j);
+    }
+    if (count > p->many_cap) {
+        // the previous call may still write its status words
+        for (hipEvent_t j : p->slot_join)
+            if ((e = hipEventSynchronize(j)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        (void)hipFree(p->d_many_status);
+        p->d_many_status = nullptr;
+        p->many_cap = 0;
+        if ((e = hipMalloc(&p->d_many_status, size_t(count) * sizeof(int))) != hipSuccess)
+            return fail(GS_ENOMEM, std::string("gs_score_all_many: status words: ") +
+                                       hipGetErrorString(e));
+        p->many_cap = count;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if ((e = hipEventRecord(p->fork, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    for (int j = 0; j < in_flight; ++j)
+        if ((e = hipStreamWaitEvent(p->slot_streams[j], p->fork, 0)) != hipSuccess)
+            return hip_fail(e, "hipStreamWaitEvent");
+    st = GS_OK;
+    for (int i = 0; i < count && st == GS_OK; ++i) {
+        const int j = i % in_flight;
+        gs_plan_s *q = j == 0 ? p : p->slots[j - 1];
+        st = score_all_impl<float>(q, X[i], n, p->m, ldx, scores[i], what, p->slot_streams[j], who);
+        if (st == GS_OK &&
+            (e = hipMemcpyAsync(p->d_many_status + i, q->d_status, sizeof(int),
+                                hipMemcpyDeviceToDevice, p->slot_streams[j])) != hipSuccess)
+            st = hip_fail(e, "status copy");
+    }
+    // join, also after an error: the caller's stream waits for whatever was enqueued
+    for (int j = 0; j < in_flight; ++j)
+        if ((e = hipEventRecord(p->slot_join[j], p->slot_streams[j])) != hipSuccess ||
+            (e = hipStreamWaitEvent(s, p->slot_join[j], 0)) != hipSuccess)
+            return hip_fail(e, "stream join");
+    p->many_count = st == GS_OK ? count : 0;
+    return st;
+}
+
+int gs_many_status(gs_plan_t *p, int *status) {
+    if (!p || !status) return fail(GS_EINVAL, "gs_many_status: NULL argument");
+    if (p->many_count == 0)
+        return fail(GS_EINVAL, "gs_many_status: no completed gs_score_all_many call on this plan");
+    hipError_t e;
+    for (hipEvent_t j : p->slot_join)
+        if ((e = hipEventSynchronize(j)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    std::vector<int> flags(size_t(p->many_count));
+    if ((e = hipMemcpy(flags.data(), p->d_many_status, flags.size() * sizeof(int),
+                       hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "status copy");
+    int first = GS_OK;
+    for (size_t i = 0; i < flags.size(); ++i) {
+        const int f = flags[i];
+        status[i] = (f & GS_FLAG_NOTFINITE) ? GS_ENOTFINITE
+                    : (f & GS_FLAG_RANK)    ? GS_ERANK
+                    : (f & GS_FLAG_RANGE)   ? GS_ERANGE
+                                            : GS_OK;
+        if (status[i] != GS_OK && first == GS_OK) {
+            first = status[i];
+            set_error("gs_many_status: dataset " + std::to_string(i) + " has status " +
+                      std::to_string(first));
+        }
+    }
+    return first;
 }
 
 int gs_qr_r0(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx, double *R0,

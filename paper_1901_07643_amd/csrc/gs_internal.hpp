@@ -97,6 +97,14 @@ struct gs_plan_s {
     int beta_k = 0;
     hipStream_t last_stream = nullptr;
     hipEvent_t done = nullptr;
+    // gs_score_all_many: the extra in-flight workspaces (plans with the same program),
+    // one stream and join event per slot, the fork event and per-dataset status words
+    std::vector<gs_plan_s *> slots;
+    std::vector<hipStream_t> slot_streams;
+    std::vector<hipEvent_t> slot_join;
+    hipEvent_t fork = nullptr;
+    int *d_many_status = nullptr;
+    int64_t many_cap = 0, many_count = 0;
 
     bool timing = false;
     std::vector<std::array<hipEvent_t, 4>> events;

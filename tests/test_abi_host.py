@@ -83,6 +83,29 @@ def _plans():
     return out
 
 
+def test_many_argument_errors_before_device_work(gs):
+    """gs_score_all_many rejects bad arguments before it touches the device (the
+    pointers here are never dereferenced)."""
+    L = gs.lib()
+    p = gs.Plan(6)
+    vp = ctypes.c_void_p
+    xs = (vp * 2)(4096, 8192)
+    outs = (vp * 2)(4096, 8192)
+    bad = (vp * 2)(4096, 4100)  # second table not 16-byte aligned
+    assert L.gs_score_all_many(p.handle, 0, xs, 50, 6, outs, 0, 2, None) == gs.GS_EINVAL
+    assert L.gs_score_all_many(p.handle, 2, xs, 50, 6, outs, 0, 0, None) == gs.GS_EINVAL
+    assert L.gs_score_all_many(p.handle, 2, xs, 50, 6, outs, 0, 9, None) == gs.GS_EINVAL
+    assert L.gs_score_all_many(p.handle, 2, None, 50, 6, outs, 0, 2, None) == gs.GS_EINVAL
+    assert L.gs_score_all_many(p.handle, 2, xs, 50, 6, None, 0, 2, None) == gs.GS_EINVAL
+    assert L.gs_score_all_many(p.handle, 2, xs, 50, 6, bad, 0, 2, None) == gs.GS_EINVAL
+    assert L.gs_score_all_many(p.handle, 2, xs, 6, 6, outs, 0, 2, None) == gs.GS_EINVAL
+    assert L.gs_score_all_many(p.handle, 2, xs, 50, 6, outs, 7, 2, None) == gs.GS_EINVAL
+    assert L.gs_score_all_many(None, 2, xs, 50, 6, outs, 0, 2, None) == gs.GS_EINVAL
+    st = (ctypes.c_int * 2)()
+    assert L.gs_many_status(p.handle, st) == gs.GS_EINVAL  # no call has run
+    assert L.gs_many_status(None, st) == gs.GS_EINVAL
+
+
 @pytest.mark.parametrize("m,k,ks", _plans())
 def test_plan_covers_every_family_once(gs, m, k, ks):
     p = gs.Plan(m, k, ks)
