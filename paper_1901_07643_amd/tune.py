@@ -10,11 +10,72 @@ real calls on synthetic data of the requested shapes.
     k = tune_plan(26, 5000)                 # best k for one dataset shape
     caps = tune_batch([(m0, n0), ...])      # best common cap on k for a batch
 
-Results are kept in a per-process cache keyed by shape.
+Results are kept in a per-process cache keyed by shape and, when GS_TUNE_CACHE names a
+file (or the default ~/.cache/givscore/tune.json is writable), in a JSON file keyed by
+the GPU architecture, the library build and the shapes, so that later processes on the
+same kind of device skip the timing.  GS_TUNE_CACHE=off disables the file.
 """
 from __future__ import annotations
 
+import hashlib
+import json
+import os
+
 _CACHE: dict = {}
+
+
+def _cache_path():
+    p = os.environ.get("GS_TUNE_CACHE")
+    if p == "off":
+        return None
+    return p or os.path.join(os.path.expanduser("~"), ".cache", "givscore", "tune.json")
+
+
+def _file_key(key, device) -> str:
+    """Stable text key: architecture, library build, and the in-process key."""
+    import torch
+
+    from ._abi import LIB_PATH
+    props = torch.cuda.get_device_properties(device or "cuda")
+    arch = getattr(props, "gcnArchName", props.name)
+    try:
+        st = os.stat(LIB_PATH)
+        build = f"{st.st_size}:{int(st.st_mtime)}"
+    except OSError:
+        build = "?"
+    return hashlib.sha256(repr((arch, build, key)).encode()).hexdigest()[:32]
+
+
+def _file_get(key, device):
+    path = _cache_path()
+    if not path:
+        return None
+    try:
+        with open(path) as f:
+            val = json.load(f).get(_file_key(key, device))
+    except (OSError, ValueError):
+        return None
+    return val
+
+
+def _file_put(key, device, value) -> None:
+    path = _cache_path()
+    if not path:
+        return
+    try:
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        try:
+            with open(path) as f:
+                data = json.load(f)
+        except (OSError, ValueError):
+            data = {}
+        data[_file_key(key, device)] = value
+        tmp = f"{path}.{os.getpid()}.tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only home: the in-process cache still holds the result
 
 # FP32 accuracy limit on the walk length from its FP64 start (see the plan defaults)
 K_MAX_FP32 = 13
@@ -53,6 +114,10 @@ def tune_plan(m: int, n: int, candidates=None, reps: int = 5, device=None, seed:
     key = ("plan", m, n, what, tuple(candidates) if candidates else None)
     if key in _CACHE:
         return _CACHE[key]
+    hit = _file_get(key, device)
+    if isinstance(hit, int):
+        _CACHE[key] = hit
+        return hit
     dev = torch.device(device or "cuda")
     g = torch.Generator(device="cpu").manual_seed(seed)
     X = torch.randn((n, m), generator=g, dtype=torch.float64).to(dev)
@@ -66,6 +131,7 @@ def tune_plan(m: int, n: int, candidates=None, reps: int = 5, device=None, seed:
             best, best_ms = k, ms
         plan.close()
     _CACHE[key] = best
+    _file_put(key, device, best)
     return best
 
 
@@ -85,6 +151,11 @@ def tune_batch(shapes, caps=None, reps: int = 5, device=None, seed: int = 0,
     key = ("batch", tuple(shapes), what, tuple(caps) if caps else None)
     if key in _CACHE:
         return _CACHE[key]
+    hit = _file_get(key, device)
+    if isinstance(hit, list) and len(hit) == 2 and isinstance(hit[1], dict):
+        val = (int(hit[0]), {int(c): float(t) for c, t in hit[1].items()})
+        _CACHE[key] = val
+        return val
     dev = torch.device(device or "cuda")
     g = torch.Generator(device="cpu").manual_seed(seed)
     Xs = [torch.randn((n, m), generator=g, dtype=torch.float64).to(dev) for m, n in shapes]
@@ -99,6 +170,7 @@ def tune_batch(shapes, caps=None, reps: int = 5, device=None, seed: int = 0,
         b.close()
     best = min(times, key=times.get)
     _CACHE[key] = (best, times)
+    _file_put(key, device, [best, {str(c): t for c, t in times.items()}])
     return best, times
 
 

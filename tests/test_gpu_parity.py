@@ -358,6 +358,21 @@ def test_row_blocks_at_different_scales(gs, n):
     print(f"\nrow blocks at 2^[-20, 20], n={n}: FP64 max rel RSS err {err:.3e}")
 
 
+def test_column_zero_in_some_row_blocks(gs):
+    """A column that is exactly zero in the first two 128-row blocks (the first QR pass
+    then has no exponent for it there) and another that is zero outside them: the
+    rescaling pass must keep those rows at zero.  Both walks against the oracle."""
+    m, n = 6, 700
+    X = linear_gaussian(m, n, 0.3, 0.5, 1.5, seed=71)
+    X[:256, 2] = 0.0
+    X[256:, 4] = 0.0
+    ref = oracle.score_all(X, oracle.OUT_RSS)
+    for prec in ("fp64", "fp32"):
+        got = _run(gs, X, "rss", prec).cpu().numpy()
+        err = _assert_rss(got, ref, TOL[prec], f"zero column blocks {prec}")
+        print(f"\ncolumns zero in some row blocks, {prec}: max rel RSS err {err:.3e}")
+
+
 def test_tiny_column_is_not_rank_deficient(gs):
     """One column in units 1e-13 smaller than the others: well posed (the rank test is
     scale free), both walks within their tolerances."""
