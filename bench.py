@@ -415,14 +415,24 @@ def main():
         gs.score_all(X, plan=plan, what="bic", precision="fp64", out=out64, check_status=False)
         torch.cuda.synchronize()
         k64 = max(2, args.steps // 4)
+        plan.set_timing(True)
         e0.record(stream)
         for _ in range(k64):
             gs.score_all(X, plan=plan, what="bic", precision="fp64", out=out64, check_status=False)
         e1.record(stream)
         torch.cuda.synchronize()
         ms64 = e0.elapsed_time(e1) / k64
+        st64, cnt64 = plan.timing()
+        plan.set_timing(False)
+        walk64_ms = st64[2] if cnt64 else None
         res["fp64_walk"] = {"value": nfam / (ms64 * 1e-3), "unit": "families/s",
                             "ms_per_step": ms64, "steps": k64}
+        if walk64_ms:
+            gbs = 8.0 * nfam / (walk64_ms * 1e-3) / 1e9
+            res["fp64_walk"]["roofline"] = {
+                "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "kernel": "walk_kernel<double,5,true,1>",
+                "kernel_ms": walk64_ms, "note": "8 B per family (the FP64 table write)"}
         gs.score_all(X, plan=plan, what="rss", precision="fp64", out=out64, check_status=False)
         gs.score_all(X, plan=plan, what="rss", precision="fp32", out=out, check_status=False)
         worst = 0.0
