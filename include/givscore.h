@@ -213,9 +213,10 @@ int gs_score_all_static(gs_plan_t *plan, const double *X, int64_t n, int m, int6
  *     gs_family_index); every table is bit-identical to gs_score_all on X[i] alone;
  *   what: GS_OUT_BIC or GS_OUT_RSS; in_flight: 1..GS_MANY_MAX_IN_FLIGHT.
  * The arrays X and scores are host arrays of device pointers, read during the call.
- * gs_many_status gives each dataset's status.  Errors: GS_EINVAL on bad arguments
- * (before any device work), GS_ENOMEM; an error after some datasets were enqueued
- * still makes `stream` wait for them. */
+ * gs_many_status gives each dataset's status (gs_sync_status does not cover this call).
+ * As for every call on a plan, calls that overlap on one plan race (the slots are the
+ * plan's).  Errors: GS_EINVAL on bad arguments (before any device work), GS_ENOMEM; an
+ * error after some datasets were enqueued still makes `stream` wait for them. */
 #define GS_MANY_MAX_IN_FLIGHT 8
 int gs_score_all_many(gs_plan_t *plan, int count, const double *const *X, int64_t n,
                       int64_t ldx, float *const *scores, int what, int in_flight, void *stream);
