@@ -76,3 +76,16 @@ def test_many_on_a_side_stream(gs):
     s.synchronize()
     want = torch.stack([gs.score_all(X).double().sum() for X in Xs])
     assert torch.equal(sums.cpu(), want.cpu())
+
+
+def test_many_with_strided_rows(gs):
+    """Datasets that are column slices of wider arrays (row stride > m)."""
+    m, n = 7, 90
+    wide = [torch.as_tensor(linear_gaussian(m + 3, n, 0.3, 0.5, 1.5, seed=60 + i), device="cuda")
+            for i in range(3)]
+    Xs = [w[:, :m] for w in wide]
+    assert Xs[0].stride(0) == m + 3
+    plan = gs.Plan(m)
+    outs = gs.score_all_many(Xs, plan=plan, what="rss", in_flight=2)
+    for X, got in zip(Xs, outs):
+        assert torch.equal(got, gs.score_all(X.contiguous(), what="rss"))
