@@ -348,7 +348,10 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
     // the child's equilibration exponent: BIC offset, RSS factor 2^(2 e_c)
     const int ec2 = label >= 0 ? 2 * stats->exp2[label] : 0;
     const T coff = T(a.nln2 * double(ec2));
-    bool out_of_range = false;  // RSS output only: a value outside the normal range
+    // RSS output only: the largest residual and the smallest non-zero one the lane scored.
+    // ldexp by the fixed 2^(2 e_c) never decreases, so some scaled value overflows or a
+    // non-zero one underflows exactly when these two do (tested once, after the walk).
+    T rss_hi = T(0), rss_lo = T(INFINITY);
     // reduce modes: running minimum, its parent set, sum of exp(min - BIC), top values
     float rmin = __builtin_inff(), rsum = 0.0f;
     uint32_t rmask = 0;
@@ -434,11 +437,9 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
             if constexpr (BIC) {
                 return Arith<T>::score(rss, nlog, cst[u]);
             } else {
-                const T v = Arith<T>::ldexp(rss, ec2);
-                // an overflow, or an underflow of a non-zero residual (to a subnormal or 0)
-                out_of_range = out_of_range || v > Arith<T>::huge() ||
-                               (v < Arith<T>::tiny() && rss != T(0));
-                return v;
+                rss_hi = fmax(rss_hi, rss);
+                rss_lo = fmin(rss_lo, rss > T(0) ? rss : T(INFINITY));
+                return Arith<T>::ldexp(rss, ec2);
             }
         };
         static_for<0, KS + 1>([&](auto pc) {
@@ -647,6 +648,9 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
         }
     }
     if constexpr (!BIC) {
+        // an overflow, or an underflow of a non-zero residual (to a subnormal or 0)
+        const bool out_of_range = Arith<T>::ldexp(rss_hi, ec2) > Arith<T>::huge() ||
+                                  Arith<T>::ldexp(rss_lo, ec2) < Arith<T>::tiny();
         if (__builtin_amdgcn_ballot_w64(out_of_range && seg_ok) != 0 && lane64 == 0)
             atomicOr(const_cast<int *>(status), GS_FLAG_RANGE);
     }
@@ -719,8 +723,14 @@ void walk_batched_kernel(const BatchItem *__restrict__ items, const int32_t *__r
 template <typename T, int KS>
 constexpr int kMinWaves = !std::is_same_v<T, float> ? 1 : (KS == 5 ? 4 : (KS < 5 ? WALK_MIN_WAVES : 1));
 // the top-k reduction keeps 16 more values per lane and has no line stage: 168 VGPRs
+// with inner block 5, 128 with smaller ones
 template <typename T, int KS, int MODE>
-constexpr int kMinWavesMode = (MODE == WALK_REDUCE_TOP && KS == 5) ? 3 : kMinWaves<T, KS>;
+constexpr int kMinWavesMode =
+    MODE == WALK_REDUCE_TOP ? (KS == 5 ? 3 : (KS < 5 ? 4 : 1)) : kMinWaves<T, KS>;
+// the FP32 RSS table with inner block 5 gets 168 VGPRs too: held to 128 it spilled to
+// scratch and took three times as long as the BIC walk
+template <typename T, int KS, bool BIC, int MODE>
+constexpr int kMinW = (!BIC && std::is_same_v<T, float> && KS == 5) ? 3 : kMinWavesMode<T, KS, MODE>;
 
 template <typename T, bool BIC, int MODE = WALK_STORE>
 static hipError_t launch_walk_t(const gs_plan_s *p, const WalkTables &t, const T *anchor,
@@ -746,7 +756,7 @@ static hipError_t launch_walk_t(const gs_plan_s *p, const WalkTables &t, const T
     switch (p->ks) {
 #define GS_WALK_CASE(KSV)                                                                   \
     case KSV:                                                                               \
-        hipLaunchKernelGGL((walk_kernel<T, KSV, BIC, kMinWavesMode<T, KSV, MODE>, MODE>), grid,  \
+        hipLaunchKernelGGL((walk_kernel<T, KSV, BIC, kMinW<T, KSV, BIC, MODE>, MODE>), grid,  \
                            block, lds,                                                         \
                            s,                                                                  \
                            anchor, tail,                                                    \
@@ -773,7 +783,7 @@ hipError_t launch_walk_batched_f32(const BatchItem *items, const int32_t *wave_i
         hipLaunchKernelGGL((walk_batched_kernel<float, 5, true, kMinWaves<float, 5>>), grid, block, lds,
                            s, items, wave_item, wave_local, total_waves, qmax);
     else
-        hipLaunchKernelGGL((walk_batched_kernel<float, 5, false, kMinWaves<float, 5>>), grid, block,
+        hipLaunchKernelGGL((walk_batched_kernel<float, 5, false, kMinW<float, 5, false, WALK_STORE>>), grid, block,
                            lds, s, items, wave_item, wave_local, total_waves, qmax);
     return hipGetLastError();
 }
