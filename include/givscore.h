@@ -257,7 +257,7 @@ int gs_score_all_f64(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t
  * (table order; the score is BIC or RSS as selected by `what`), writes
  * dX = d(loss)/dX.  Not in the paper: the adjoint of its method.
  *   X: device, the same n x m FP64 data as for gs_score_all (row stride ldx).
- *   dscores: device, m * 2^(m-1) floats.
+ *   dscores: device, m * 2^(m-1) floats, 16-byte aligned (GS_EINVAL otherwise).
  *   dX: device, n x m FP64, row stride lddx >= m; overwritten.
  * The FP32 walk is replayed and then undone step by step in FP32: every Givens step
  * is recovered from the rotated matrix, nothing is stored per step.  The reverse
@@ -267,7 +267,7 @@ int gs_score_all_f64(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t
 int gs_score_backward(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
                       const float *dscores, int what, double *dX, int64_t lddx, void *stream);
 
-/* Same with the walk replayed and undone in FP64 and FP64 dscores. */
+/* Same with the walk replayed and undone in FP64 and FP64 dscores (16-byte aligned). */
 int gs_score_backward_f64(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
                           const double *dscores, int what, double *dX, int64_t lddx,
                           void *stream);

@@ -52,12 +52,52 @@ __device__ __forceinline__ double bcast_r(double v, int addr) {
                                             (unsigned long long)(unsigned)lo));
 }
 
-// sum over the 32 lanes of this half-wave (one segment)
+// Cross-lane moves for half_sum: DPP inside a 16-lane row (no LDS round trip), and
+// ds_swizzle for lane ^ 16 inside each 32-lane group.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_r(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_r(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL>(int(b & 0xffffffffll)), hi = dpp_i<CTRL>(int(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned long long)(unsigned)lo));
+}
+constexpr int SWZ_XOR16 = 0x1F | (0x10 << 10);  // bitmask mode: and 0x1F, or 0, xor 0x10
+__device__ __forceinline__ float xor16_r(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), SWZ_XOR16));
+}
+__device__ __forceinline__ double xor16_r(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_swizzle(int(b & 0xffffffffll), SWZ_XOR16);
+    const int hi = __builtin_amdgcn_ds_swizzle(int(b >> 32), SWZ_XOR16);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned long long)(unsigned)lo));
+}
+
+// sum over the 32 lanes of this half-wave (one segment), in every lane: pairs (lane ^ 1),
+// quads (lane ^ 2), the two quads of each 8 (mirror inside 8), the two 8s of each row
+// (mirror inside 16), then the two rows (lane ^ 16)
 template <typename T>
 __device__ __forceinline__ T half_sum(T v) {
-#pragma unroll
-    for (int off = 16; off >= 1; off >>= 1) v += __shfl_xor(v, off, 32);
-    return v;
+    v += dpp_r<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_r<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_r<0x141>(v);  // row_half_mirror
+    v += dpp_r<0x140>(v);  // row_mirror
+    return v + xor16_r(v);
+}
+
+// 1 / x: the hardware reciprocal in FP32 (within 1 ulp), a division in FP64
+template <typename T>
+__device__ __forceinline__ T recip_r(T x) {
+    if constexpr (std::is_same_v<T, float>) return __builtin_amdgcn_rcpf(x);
+    else return 1.0 / x;
 }
 
 template <typename T>
@@ -98,6 +138,28 @@ __device__ __forceinline__ int max_exp2(const ColStats *st, int m) {
 
 constexpr int ADJ_HALVES = 4;  // segments per 128-thread workgroup
 
+// NS consecutive cotangents of one table line with 16-byte loads.  A line starts at a
+// multiple of NS entries of the 16-byte aligned table, so the loads are aligned.
+template <typename T, int NS>
+__device__ __forceinline__ void load_line(const T *__restrict__ src, T (&v)[NS]) {
+    constexpr int VW = 16 / int(sizeof(T));
+    if constexpr (NS % VW == 0) {
+        typedef T VT __attribute__((ext_vector_type(VW)));
+        const VT *p = reinterpret_cast<const VT *>(src);
+        static_for_r<0, NS / VW>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const VT w = p[i];
+            static_for_r<0, VW>([&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                v[i * VW + e] = w[e];
+            });
+        });
+    } else {
+#pragma unroll
+        for (int U = 0; U < NS; ++U) v[U] = src[U];
+    }
+}
+
 // Forward Givens step on rows (x, y) with pivot lane address paddr (the column moving
 // from j+1 to j); the pivot's new row-(j+1) entry is set to exactly zero.
 template <typename T>
@@ -128,10 +190,11 @@ __device__ __forceinline__ void rev_step(T &x, T &y, T &xb, T &yb, int paddr, in
     T yb0 = s * xba - c * yba;
     const T cb = half_sum(xba * x0 - yba * y0);
     const T sb = half_sum(xba * y0 + yba * x0);
-    if (is_piv && rho != T(0)) {
-        xb0 += s * (cb * s - sb * c) / rho;
-        yb0 += c * (sb * c - cb * s) / rho;
-    }
+    // the pivot lane carries the adjoints of c and s (through rho) back to its rows
+    const T rinv = (is_piv && rho != T(0)) ? recip_r(rho) : T(0);
+    const T t = (cb * s - sb * c) * rinv;
+    xb0 += s * t;
+    yb0 -= c * t;
     x = x0;
     y = y0;
     xb = xb0;
@@ -272,18 +335,18 @@ __global__ __launch_bounds__(32 * ADJ_HALVES) void walk_adjoint_kernel(const T *
             lbase = cbase + int64_t(lo | hi);
         }
 #pragma unroll
-        for (int U = 0; U < NS; ++U) {
-            T g = T(0);
-            if (cls == 1) {
+        for (int U = 0; U < NS; ++U) gl[U] = T(0);
+        if (cls == 1) {
+            // inner child: the entries without its own bit, gathered
+#pragma unroll
+            for (int U = 0; U < NS; ++U) {
                 if (!((U >> lane) & 1)) {
                     const int lowm = (1 << lane) - 1;
-                    const int cu = (U & lowm) | ((U >> (lane + 1)) << lane);
-                    g = dscores[lbase + cu];
+                    gl[U] = dscores[lbase + ((U & lowm) | ((U >> (lane + 1)) << lane))];
                 }
-            } else if (child) {
-                g = dscores[lbase + U];
             }
-            gl[U] = g;
+        } else if (child) {
+            load_line<T, NS>(dscores + lbase, gl);  // its whole line
         }
         T bsum = tl;
         for (int p = q - 1; p >= z; --p) bsum = L[p][lane] * L[p][lane] + bsum;
@@ -297,7 +360,7 @@ __global__ __launch_bounds__(32 * ADJ_HALVES) void walk_adjoint_kernel(const T *
         // zero RSS), which must stay 0: a NaN would reach every lane through the sums
         // of the rotation adjoints
         auto gbar = [&](T rss, T g) -> T {
-            return (a.bic && g != T(0)) ? g * nn / rss : g * gscale;
+            return (a.bic && g != T(0)) ? g * nn * recip_r(rss) : g * gscale;
         };
         static_for_r<0, N>([&](auto sc) {
             constexpr int st = N - 1 - decltype(sc)::value;

@@ -244,6 +244,8 @@ int score_backward_impl(gs_plan_s *p, const double *X, int64_t n, int m, int64_t
     int st = check_common(p, X, n, m, ldx, dX, who);
     if (st != GS_OK) return st;
     if (!dscores) return fail(GS_EINVAL, std::string(who) + ": dscores is NULL");
+    if (reinterpret_cast<uintptr_t>(dscores) % 16 != 0)
+        return fail(GS_EINVAL, std::string(who) + ": dscores must be 16-byte aligned");
     if (lddx < m) return fail(GS_EINVAL, std::string(who) + ": lddx < m");
     if (what != GS_OUT_BIC && what != GS_OUT_RSS)
         return fail(GS_EINVAL, std::string(who) + ": what must be GS_OUT_BIC or GS_OUT_RSS");

@@ -106,6 +106,19 @@ def test_many_argument_errors_before_device_work(gs):
     assert L.gs_many_status(None, st) == gs.GS_EINVAL
 
 
+def test_backward_argument_errors_before_device_work(gs):
+    """gs_score_backward rejects a NULL or misaligned dscores (the line loads of the
+    walk adjoint are 16 bytes wide) before it touches the device."""
+    L = gs.lib()
+    p = gs.Plan(6)
+    vp = ctypes.c_void_p
+    for fn in (L.gs_score_backward, L.gs_score_backward_f64):
+        assert fn(p.handle, vp(4096), 50, 6, 6, None, 0, vp(8192), 6, None) == gs.GS_EINVAL
+        assert fn(p.handle, vp(4096), 50, 6, 6, vp(4100), 0, vp(8192), 6, None) == gs.GS_EINVAL
+        assert "16-byte aligned" in gs.last_error()
+        assert fn(p.handle, vp(4096), 50, 6, 6, vp(4096), 0, vp(8200), 6, None) == gs.GS_EINVAL
+
+
 @pytest.mark.parametrize("m,k,ks", _plans())
 def test_plan_covers_every_family_once(gs, m, k, ks):
     p = gs.Plan(m, k, ks)
