@@ -201,8 +201,14 @@ __device__ __forceinline__ void rev_step(T &x, T &y, T &xb, T &yb, int paddr, in
     yb = yb0;
 }
 
+// FP32 with inner block 5: 128 VGPRs, 4 waves per SIMD, so that the 2^(m-k) / 2 waves of
+// the headline split (k = 13) are resident at once
 template <typename T, int KS>
-__global__ __launch_bounds__(32 * ADJ_HALVES) void walk_adjoint_kernel(const T *__restrict__ anchor,
+constexpr int kAdjMinWaves = (std::is_same_v<T, float> && KS == 5) ? 4 : 1;
+
+template <typename T, int KS>
+__global__ __launch_bounds__(32 * ADJ_HALVES)
+__attribute__((amdgpu_waves_per_eu(kAdjMinWaves<T, KS>, 8))) void walk_adjoint_kernel(const T *__restrict__ anchor,
                                                           const T *__restrict__ tail,
                                                           const uint32_t *__restrict__ prog,
                                                           const T *__restrict__ dscores,
