@@ -363,6 +363,32 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
         tm[j] = 0xffffffffu;
     }
 
+    // FP32, inner block 5, table written: the lines of a sub-walk wait in the LDS stage and
+    // leave during the next sub-walk, one 16-byte store instruction (8 whole lines) every
+    // three inner steps, so that the waves' stores are spread over the walk instead of
+    // coming all at once at the end of each sub-walk
+    constexpr bool kStaged =
+        std::is_same_v<T, float> && KS == 5 && (MODE == WALK_STORE || MODE == WALK_COUNT);
+    const int ch = lane64 & 7;
+    uint64_t pd = 0;
+    float4 pv = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto stage_read = [&](int ci, uint64_t &d, float4 &v) {
+        const int ow = 8 * ci + (lane64 >> 3);
+        d = Dg[ow];
+        v = Sg[ch * STAGE_LINES + (ow ^ ch)];
+    };
+    auto stage_store = [&](uint64_t d, const float4 &v) {
+        if (ch < int(d & 15u)) {
+            const uint64_t dst = (d & ~uint64_t(15)) + uint64_t(ch) * 16;
+            if constexpr (MODE == WALK_COUNT) count16(dst);
+            else global_store16(dst, v);
+        }
+    };
+    if constexpr (kStaged) {
+        Dg[lane64] = 0;  // nothing staged before the first sub-walk
+        wave_lds_sync();
+    }
+
     int z = q;
     // One sub-walk: the transition into it, the inner walk, the table writes.  FWD is
     // the direction of the inner walk (forward on even t), which fixes the inner
@@ -461,6 +487,13 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
             I[J + 1] = ny;
             sfx[J + 1] = ny * ny + sfx[J + 2];
             o[U] = score(sfx[J + 1], popcount_c(U));
+            if constexpr (kStaged) {
+                // chunk i of the previous sub-walk's lines: read from the stage after
+                // step 3i + 1, stored after step 3i + 2 (the read has completed by then)
+                constexpr int ci = st / 3;
+                if constexpr (ci < STAGE_CHUNKS && st % 3 == 1) stage_read(ci, pd, pv);
+                if constexpr (ci < STAGE_CHUNKS && st % 3 == 2) stage_store(pd, pv);
+            }
         });
 
         if constexpr (MODE == WALK_REDUCE || MODE == WALK_REDUCE_TOP) {
@@ -590,24 +623,8 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
             const uint64_t inner_dst = reinterpret_cast<uint64_t>(out + cbase + int64_t(Shi >> 1)) | (NH / 4);
             const uint64_t line_dst = reinterpret_cast<uint64_t>(out + cbase + int64_t(low | high)) | (NS / 4);
             Dg[lane64] = cls == 1 ? inner_dst : (child ? line_dst : 0);
-            wave_lds_sync();
-            const int ch = lane64 & 7;
-            uint64_t dd[8];
-            float4 vv[8];
-            static_for<0, 8>([&](auto tc) {
-                constexpr int t = decltype(tc)::value;
-                const int ow = 8 * t + (lane64 >> 3);
-                dd[t] = Dg[ow];
-                vv[t] = Sg[ch * STAGE_LINES + (ow ^ ch)];
-            });
-            static_for<0, 8>([&](auto tc) {
-                constexpr int t = decltype(tc)::value;
-                if (ch < int(dd[t] & 15u)) {
-                    const uint64_t dst = (dd[t] & ~uint64_t(15)) + uint64_t(ch) * 16;
-                    if constexpr (MODE == WALK_COUNT) count16(dst);
-                    else global_store16(dst, vv[t]);
-                }
-            });
+            wave_lds_sync();  // staged before any later read of the stage
+            // the stores leave during the next sub-walk's inner steps (or after the walk)
         } else {
             if (cls == 1) {
                 T h[NH];
@@ -632,6 +649,14 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
     // guarded path.
     if (std::is_same_v<T, double> || (status[0] & GS_FLAG_GUARD)) run(std::true_type{});
     else run(std::false_type{});
+    if constexpr (kStaged) {
+        wave_lds_sync();  // the last sub-walk's lines are in the stage
+        static_for<0, STAGE_CHUNKS>([&](auto cc) {
+            constexpr int ci = decltype(cc)::value;
+            stage_read(ci, pd, pv);
+            stage_store(pd, pv);
+        });
+    }
     if constexpr (MODE == WALK_REDUCE || MODE == WALK_REDUCE_TOP) {
         if (seg_ok && cls != 0) {
             const int64_t r = int64_t(label) * a.nseg + segv;
