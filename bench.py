@@ -22,7 +22,8 @@ Prints one JSON line.  Besides the contract fields it carries
                 gs_score_batched, with the autotuned cap on k, against 256 sequential
                 gs_score_all calls with the same plans;
   adjoint       forward + hand-written backward at m = 14, n = 500 (the loss
-                sum_c logsumexp_S(-BIC));
+                sum_c logsumexp_S(-BIC)); the backward takes R0 and the anchors from
+                the forward, as in a training step (bwd_full_ms: forming them again);
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload, with the
                 largest difference between those oracle values and the GPU table
                 (measured after the timed region);
@@ -271,14 +272,20 @@ def bench_adjoint(steps: int, stream):
     gs.score_backward(X, dbic, plan=plan, out=dX)
     ms_fwd = _event_ms(lambda: gs.score_all(X, plan=plan, out=bic, check_status=False), steps,
                        stream)
-    ms_bwd = _event_ms(lambda: gs.score_backward(X, dbic, plan=plan, out=dX, check_status=False),
-                       steps, stream)
+    # a training step runs the forward, then the backward on the same X: the backward takes
+    # R0 and the anchors the forward left in the plan (gs_plan_set_reuse)
+    ms_bwd = _event_ms(lambda: gs.score_backward(X, dbic, plan=plan, out=dX, check_status=False,
+                                                 reuse_front=True), steps, stream)
+    ms_bwd_full = _event_ms(lambda: gs.score_backward(X, dbic, plan=plan, out=dX,
+                                                      check_status=False, reuse_front=False),
+                            steps, stream)
     out64 = torch.empty(nfam, dtype=torch.float64, device="cuda")
     gs.score_all(X, plan=plan, out=out64, precision="fp64")
     ms_fwd64 = _event_ms(lambda: gs.score_all(X, plan=plan, out=out64, precision="fp64",
                                               check_status=False), steps, stream)
     bwd_bytes = 4.0 * nfam + 8.0 * 2 * n * m  # dscores read once; X read, dX written
     res = {"workload": "c5_m14_n500", "families": nfam, "fwd_ms": ms_fwd, "bwd_ms": ms_bwd,
+           "bwd_full_ms": ms_bwd_full,
            "value": nfam / ((ms_fwd + ms_bwd) * 1e-3), "unit": "families/s (fwd+bwd)",
            "bwd_over_fwd": ms_bwd / ms_fwd,
            "fp64_walk_value": nfam / (ms_fwd64 * 1e-3), "fp64_walk_ms": ms_fwd64,
@@ -458,7 +465,8 @@ def main():
               file=sys.stderr, flush=True)
     if not args.no_adjoint:
         res["adjoint"] = bench_adjoint(args.steps, stream)
-        print(f"# adjoint: fwd {res['adjoint']['fwd_ms']:.4f} ms, bwd {res['adjoint']['bwd_ms']:.4f} ms",
+        print(f"# adjoint: fwd {res['adjoint']['fwd_ms']:.4f} ms, bwd {res['adjoint']['bwd_ms']:.4f} ms"
+              f" (forming R0 and the anchors again: {res['adjoint']['bwd_full_ms']:.4f} ms)",
               file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:

@@ -272,6 +272,17 @@ int gs_score_backward_f64(gs_plan_t *plan, const double *X, int64_t n, int m, in
                           const double *dscores, int what, double *dX, int64_t lddx,
                           void *stream);
 
+/* Reuse of the forward's intermediates by the backward (off by default).  With
+ * enable != 0, gs_score_backward (gs_score_backward_f64) takes R0 and the segment
+ * anchors from the plan's buffers instead of forming them again when the plan's last
+ * call that formed them (gs_score_all, gs_score_reduce, gs_count_writes or a backward
+ * call for the FP32 walk; gs_score_all_f64 or gs_score_backward_f64 for the FP64 walk)
+ * was given the same X pointer, n and ldx, and no call since has rewritten R0
+ * (gs_qr_r0, gs_score_beta); otherwise it forms them as usual.  The caller guarantees
+ * that X still holds the same values as in that call.  The status word is then the
+ * one that call left.  Returns GS_OK, or GS_EINVAL for a NULL plan. */
+int gs_plan_set_reuse(gs_plan_t *plan, int enable);
+
 /* Wait for the plan's last enqueued work and return GS_OK, GS_ERANK, GS_ENOTFINITE
  * or GS_ERANGE from the device status word of that call (GS_EHIP on a runtime
  * failure). */

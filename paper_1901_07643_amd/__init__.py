@@ -59,6 +59,7 @@ class Plan:
         self._h = h
         self.m = m
         self._many_count = 0
+        self._reuse = False
 
     @property
     def handle(self):
@@ -102,6 +103,13 @@ class Plan:
         out = np.zeros(self.m, dtype=np.float64)
         check(lib().gs_column_vif(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
+
+    def set_reuse(self, enable: bool = True):
+        """Let backward calls take R0 and the segment anchors from the plan's last call on
+        the same X (same pointer, n, row stride and walk precision; gs_plan_set_reuse)
+        instead of forming them again.  X must still hold the same values."""
+        check(lib().gs_plan_set_reuse(self.handle, 1 if enable else 0))
+        self._reuse = bool(enable)
 
     def set_timing(self, enable: bool = True):
         check(lib().gs_set_timing(self.handle, 1 if enable else 0))
@@ -291,11 +299,14 @@ def count_writes(X, plan: Plan | None = None, out=None):
 
 
 def score_backward(X, dscores, plan: Plan | None = None, what: str = "bic",
-                   precision: str = "fp32", out=None, check_status: bool = True):
+                   precision: str = "fp32", out=None, check_status: bool = True,
+                   reuse_front: bool | None = None):
     """d(loss)/dX (n, m) float64 from dscores = d(loss)/d(score) for every family.
 
     precision "fp32" replays and undoes the FP32 walk (dscores float32); "fp64" the FP64
-    walk (dscores float64).  The anchor and R0 QR adjoints run in FP64."""
+    walk (dscores float64).  The anchor and R0 QR adjoints run in FP64.  reuse_front
+    (None: the plan's setting, see Plan.set_reuse) takes R0 and the anchors from the
+    plan's last call on the same X, which must still hold the same values."""
     import torch
     n, m, ldx = _check_X(X, plan.m if plan else None)
     plan = plan or Plan(m)
@@ -311,10 +322,17 @@ def score_backward(X, dscores, plan: Plan | None = None, what: str = "bic",
     elif out.shape != (n, m) or out.dtype != torch.float64 or out.stride(1) != 1:
         raise ValueError("out must be an (n, m) float64 tensor with unit column stride")
     fn = lib().gs_score_backward if precision == "fp32" else lib().gs_score_backward_f64
+    override = reuse_front is not None and bool(reuse_front) != plan._reuse
     with torch.cuda.device(X.device):
-        check(fn(plan.handle, ctypes.c_void_p(X.data_ptr()), n, m, ldx,
-                 ctypes.c_void_p(dscores.data_ptr()), w, ctypes.c_void_p(out.data_ptr()),
-                 out.stride(0), _stream(X.device)))
+        if override:
+            check(lib().gs_plan_set_reuse(plan.handle, 1 if reuse_front else 0))
+        try:
+            check(fn(plan.handle, ctypes.c_void_p(X.data_ptr()), n, m, ldx,
+                     ctypes.c_void_p(dscores.data_ptr()), w, ctypes.c_void_p(out.data_ptr()),
+                     out.stride(0), _stream(X.device)))
+        finally:
+            if override:
+                lib().gs_plan_set_reuse(plan.handle, 1 if plan._reuse else 0)
         if check_status:
             check(plan.status())
     return out
@@ -420,8 +438,11 @@ def _make_function():
         def backward(ctx, dscores):
             (X,) = ctx.saved_tensors
             dtype = torch.float32 if ctx.precision == "fp32" else torch.float64
+            # autograd has checked that X was not modified since the forward, so R0 and
+            # the anchors that the forward left in the plan can be reused when nothing
+            # else has run on the plan since
             dX = score_backward(X, dscores.to(dtype).contiguous(), plan=ctx.plan, what=ctx.what,
-                                precision=ctx.precision)
+                                precision=ctx.precision, reuse_front=True)
             return dX, None, None, None
 
     return GivScore

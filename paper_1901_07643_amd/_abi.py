@@ -86,6 +86,7 @@ def lib():
         "gs_many_status": (i32, [vp, ctypes.POINTER(ctypes.c_int)]),
         "gs_score_backward": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
         "gs_score_backward_f64": (i32, [vp, vp, i64, i32, i64, vp, i32, vp, i64, vp]),
+        "gs_plan_set_reuse": (i32, [vp, i32]),
         "gs_sync_status": (i32, [vp]),
         "gs_column_vif": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
         "gs_set_timing": (i32, [vp, i32]),

@@ -164,6 +164,7 @@ template <typename T>
 int front_half(gs_plan_s *p, const double *X, int64_t n, int m, int64_t ldx, hipStream_t s,
                hipEvent_t *ev) {
     hipError_t e;
+    p->front_x = nullptr;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if ((e = launch_front_reset(p->d_status, p->d_stats, 1, s)) != hipSuccess)
         return hip_fail(e, "status reset launch");
@@ -176,6 +177,10 @@ int front_half(gs_plan_s *p, const double *X, int64_t n, int m, int64_t ldx, hip
         hipSuccess)
         return hip_fail(e, "anchor launch");
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    p->front_x = X;
+    p->front_n = n;
+    p->front_ldx = ldx;
+    p->front_elem = int(sizeof(T));
     return GS_OK;
 }
 
@@ -253,7 +258,10 @@ int score_backward_impl(gs_plan_s *p, const double *X, int64_t n, int m, int64_t
     if ((st = ensure_workspace(p, n)) != GS_OK) return st;
     if ((st = ensure_adjoint_workspace(p, n)) != GS_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if ((st = front_half<T>(p, X, n, m, ldx, s, nullptr)) != GS_OK) return st;
+    // R0 and the anchors of the plan's last call on the same data, if allowed and present
+    const bool reuse = p->reuse_front && p->front_x == X && p->front_n == n &&
+                       p->front_ldx == ldx && p->front_elem == int(sizeof(T));
+    if (!reuse && (st = front_half<T>(p, X, n, m, ldx, s, nullptr)) != GS_OK) return st;
     hipError_t e = launch_walk_adjoint<T>(p, static_cast<const T *>(p->d_anchor),
                                           static_cast<const T *>(p->d_tail), dscores,
                                           p->d_anchorbar, p->d_tailbar, n, what == GS_OUT_BIC, s);
@@ -281,6 +289,12 @@ int gs_score_backward_f64(gs_plan_t *p, const double *X, int64_t n, int m, int64
                           const double *dscores, int what, double *dX, int64_t lddx, void *stream) {
     return score_backward_impl<double>(p, X, n, m, ldx, dscores, what, dX, lddx, stream,
                                        "gs_score_backward_f64");
+}
+
+int gs_plan_set_reuse(gs_plan_t *p, int enable) {
+    if (!p) return fail(GS_EINVAL, "gs_plan_set_reuse: plan is NULL");
+    p->reuse_front = enable != 0;
+    return GS_OK;
 }
 
 
@@ -406,6 +420,7 @@ int gs_qr_r0(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx, doubl
     if (st != GS_OK) return st;
     if ((st = ensure_workspace(p, n)) != GS_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    p->front_x = nullptr;  // R0 is formed again, the anchors are not
     hipError_t e = launch_front_reset(p->d_status, p->d_stats, 1, s);
     if (e != hipSuccess) return hip_fail(e, "status reset launch");
     if ((e = launch_qr_r0(X, n, m, ldx, p->d_r0, R0, p->d_qr_a, p->d_qr_b, p->d_status, p->d_stats,
@@ -505,6 +520,7 @@ int gs_score_beta(gs_plan_t *p, const double *X, int64_t n, int m, int64_t ldx, 
         p->beta_k = k;
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    p->front_x = nullptr;  // R0 is formed again, the anchors are not
     if ((e = launch_front_reset(p->d_status, p->d_stats, 1, s)) != hipSuccess)
         return hip_fail(e, "status reset launch");
     if ((e = launch_qr_r0(X, n, m, ldx, p->d_r0, nullptr, p->d_qr_a, p->d_qr_b, p->d_status,

@@ -97,6 +97,13 @@ struct gs_plan_s {
     int beta_k = 0;
     hipStream_t last_stream = nullptr;
     hipEvent_t done = nullptr;
+    // The data whose R0 and segment anchors the plan's buffers hold: set when a front half
+    // has been enqueued in full, cleared by any call that rewrites R0.  With reuse_front
+    // the backward entry points take them from there instead of forming them again.
+    const void *front_x = nullptr;
+    int64_t front_n = 0, front_ldx = 0;
+    int front_elem = 0;  // bytes per anchor entry: 4 (FP32 walk) or 8 (FP64 walk)
+    bool reuse_front = false;
     // gs_score_all_many: the extra in-flight workspaces (plans with the same program),
     // one stream and join event per slot, the fork event and per-dataset status words
     std::vector<gs_plan_s *> slots;

@@ -119,6 +119,16 @@ def test_backward_argument_errors_before_device_work(gs):
         assert fn(p.handle, vp(4096), 50, 6, 6, vp(4096), 0, vp(8200), 6, None) == gs.GS_EINVAL
 
 
+def test_reuse_switch(gs):
+    """gs_plan_set_reuse only sets a flag of the plan (no device work)."""
+    L = gs.lib()
+    assert L.gs_plan_set_reuse(None, 1) == gs.GS_EINVAL
+    p = gs.Plan(6)
+    assert L.gs_plan_set_reuse(p.handle, 1) == gs.GS_OK
+    p.set_reuse(False)
+    assert p._reuse is False
+
+
 @pytest.mark.parametrize("m,k,ks", _plans())
 def test_plan_covers_every_family_once(gs, m, k, ks):
     p = gs.Plan(m, k, ks)
