@@ -2,8 +2,9 @@
 //
 // The paper only computes scores; the adjoint is this library's.  It runs the chain
 // X -> R0 -> segment anchors -> walk -> RSS -> score backwards:
-//   1. walk_adjoint_kernel: per segment, the walk is replayed to its end, then undone
-//      step by step.  Every Givens step is a reflector, its own inverse, and the
+//   1. walk_adjoint_kernel: per segment, the walk is replayed to its end (or, for long
+//      walks, its end state is formed directly as the R of the final ordering, one QR
+//      per segment like the anchors), then undone step by step.  Every Givens step is a reflector, its own inverse, and the
 //      rotation of a step is recovered from the matrix after the step: the column that
 //      moved from position j to j+1 holds (c x, s x) there, x > 0 its old diagonal
 //      (anchors have a non-negative diagonal and every step keeps it so).  Nothing is
@@ -208,12 +209,10 @@ constexpr int kAdjMinWaves = (std::is_same_v<T, float> && KS == 5) ? 4 : 1;
 
 template <typename T, int KS>
 __global__ __launch_bounds__(32 * ADJ_HALVES)
-__attribute__((amdgpu_waves_per_eu(kAdjMinWaves<T, KS>, 8))) void walk_adjoint_kernel(const T *__restrict__ anchor,
-                                                          const T *__restrict__ tail,
-                                                          const uint32_t *__restrict__ prog,
-                                                          const T *__restrict__ dscores,
-                                                          double *__restrict__ anchorbar,
-                                                          double *__restrict__ tailbar, AdjArgs a) {
+__attribute__((amdgpu_waves_per_eu(kAdjMinWaves<T, KS>, 8))) void walk_adjoint_kernel(
+    const T *__restrict__ anchor, const T *__restrict__ tail, const T *__restrict__ anchor_end,
+    int z_end, const uint32_t *__restrict__ prog, const T *__restrict__ dscores,
+    double *__restrict__ anchorbar, double *__restrict__ tailbar, AdjArgs a) {
     constexpr int N = InnerProgram<KS>::N;
     constexpr int NS = 1 << KS;
     __shared__ T Lrows[ADJ_HALVES][Q_MAX][32];
@@ -252,15 +251,19 @@ __attribute__((amdgpu_waves_per_eu(kAdjMinWaves<T, KS>, 8))) void walk_adjoint_k
     // lanes past the segment's k + b columns hold no column (the anchor buffer is not
     // written there): they must carry zeros, since the rotation adjoints sum over lanes
     const bool col_ok = cls != 0;
-    const T *an = anchor + int64_t(ok ? seg : 0) * k * 32 + lane;
+    // the walk's state: at its start (anchor, inner block behind all q middle rows), or
+    // with anchor_end at its end (inner block from middle row z_end on), where the
+    // reverse walk begins without a replay
+    const T *an = (anchor_end ? anchor_end : anchor) + int64_t(ok ? seg : 0) * k * 32 + lane;
+    int z = anchor_end ? z_end : q;
     T I[KS], Ib[KS];
 #pragma unroll
     for (int i = 0; i < KS; ++i) {
-        I[i] = col_ok ? an[(q + i) * 32] : T(0);
+        I[i] = col_ok ? an[(z + i) * 32] : T(0);
         Ib[i] = T(0);
     }
     for (int p = 0; p < q; ++p) {
-        L[p][lane] = col_ok ? an[p * 32] : T(0);
+        L[p][lane] = col_ok ? an[(p < z ? p : p + KS) * 32] : T(0);
         Lb[p][lane] = T(0);
     }
     const T tl = col_ok ? tail[int64_t(seg) * 32 + lane] : T(0);
@@ -271,8 +274,7 @@ __attribute__((amdgpu_waves_per_eu(kAdjMinWaves<T, KS>, 8))) void walk_adjoint_k
                          ? T(1)
                          : T(ldexp(1.0, 2 * (a.stats->exp2[label] - max_exp2(a.stats, m))));
 
-    // 1. replay the walk to its end (rotations only)
-    int z = q;
+    // 1. replay the walk to its end (rotations only), unless it starts there
     auto forward_sub = [&](auto dirc, uint32_t w1) {
         constexpr bool FWD = decltype(dirc)::value;
         constexpr auto &ord = FWD ? kInner<KS>.order_f : kInner<KS>.order_r;
@@ -316,10 +318,12 @@ __attribute__((amdgpu_waves_per_eu(kAdjMinWaves<T, KS>, 8))) void walk_adjoint_k
             fwd_step(I[J], I[J + 1], base + PV * 4, lane == PV);
         });
     };
-    for (int64_t t = 0; t < a.nsub; ++t) {
-        const uint32_t w1 = prog[2 * t + 1];
-        if ((t & 1) == 0) forward_sub(std::true_type{}, w1);
-        else forward_sub(std::false_type{}, w1);
+    if (!anchor_end) {
+        for (int64_t t = 0; t < a.nsub; ++t) {
+            const uint32_t w1 = prog[2 * t + 1];
+            if ((t & 1) == 0) forward_sub(std::true_type{}, w1);
+            else forward_sub(std::false_type{}, w1);
+        }
     }
 
     // 2. undo it, sub-walk by sub-walk
@@ -589,9 +593,9 @@ __global__ __launch_bounds__(256) void dx_kernel(const double *__restrict__ X, i
 }
 
 template <typename T>
-hipError_t launch_walk_adjoint(const gs_plan_s *p, const T *anchor, const T *tail, const T *dscores,
-                               double *anchorbar, double *tailbar, int64_t n, bool bic,
-                               hipStream_t s) {
+hipError_t launch_walk_adjoint(const gs_plan_s *p, const T *anchor, const T *tail,
+                               const T *anchor_end, const T *dscores, double *anchorbar,
+                               double *tailbar, int64_t n, bool bic, hipStream_t s) {
     AdjArgs a;
     a.m = p->m;
     a.k = p->k;
@@ -606,7 +610,7 @@ hipError_t launch_walk_adjoint(const gs_plan_s *p, const T *anchor, const T *tai
 #define GS_ADJ_CASE(KSV)                                                                     \
     case KSV:                                                                                \
         hipLaunchKernelGGL((walk_adjoint_kernel<T, KSV>), grid, block, 0, s, anchor, tail,   \
-                           p->d_prog, dscores, anchorbar, tailbar, a);                       \
+                           anchor_end, p->end.z, p->d_prog, dscores, anchorbar, tailbar, a); \
         break;
         GS_ADJ_CASE(1)
         GS_ADJ_CASE(2)
@@ -621,11 +625,11 @@ hipError_t launch_walk_adjoint(const gs_plan_s *p, const T *anchor, const T *tai
 }
 
 template hipError_t launch_walk_adjoint<float>(const gs_plan_s *, const float *, const float *,
-                                               const float *, double *, double *, int64_t, bool,
-                                               hipStream_t);
+                                               const float *, const float *, double *, double *,
+                                               int64_t, bool, hipStream_t);
 template hipError_t launch_walk_adjoint<double>(const gs_plan_s *, const double *, const double *,
-                                                const double *, double *, double *, int64_t, bool,
-                                                hipStream_t);
+                                                const double *, const double *, double *, double *,
+                                                int64_t, bool, hipStream_t);
 
 int64_t adjoint_partial_chunks(int64_t nseg) { return nseg < VSUM_CHUNKS ? nseg : VSUM_CHUNKS; }
 

@@ -21,8 +21,10 @@
 //
 // Output layout, per segment s, by column slot l (l < k: variable l; l = k + i:
 // the i-th back variable in ascending label order):
-//   anchor[s][r][l], r = 0..k-1 local rows (first the q middle rows, then the ks
-//                    inner rows), l = 0..31
+//   anchor[s][r][l], r = 0..k-1 the rows of the walked block by position (in the
+//                    starting ordering the q middle rows, then the ks inner rows; in the
+//                    final ordering of the walk, the middle rows in front of the inner
+//                    block, its ks rows, then the middle rows behind it), l = 0..31
 //   tail[s][l]     = sum of squares of column l over the back rows.
 #include <hip/hip_runtime.h>
 
@@ -36,12 +38,16 @@ namespace gs {
 
 constexpr int ANCHOR_HALVES = 8;  // segments per 256-thread workgroup
 
+// use_end: the walked block (positions d .. d+k-1) in the walk's final ordering end.order
+// instead of the starting one; tail == nullptr: no tails written (they do not change
+// along the walk).
 template <int MM, typename TO>
 __global__ __launch_bounds__(256) void anchor_kernel(const double *__restrict__ R0,
                                                      const ColStats *__restrict__ stats, int m,
                                                      int k, int ks, int64_t nseg,
                                                      TO *__restrict__ anchor,
-                                                     TO *__restrict__ tail) {
+                                                     TO *__restrict__ tail, WalkEnd end,
+                                                     int use_end) {
     __shared__ double piv_col[ANCHOR_HALVES][MM];
     const int hw = threadIdx.x >> 5;
     const int c = threadIdx.x & 31;
@@ -49,7 +55,8 @@ __global__ __launch_bounds__(256) void anchor_kernel(const double *__restrict__ 
     const bool ok = seg < nseg;
     const uint64_t s = ok ? uint64_t(seg) : 0;
     const int d = __popcll((unsigned long long)s);
-    const int label = ok ? segment_label(s, c, m, k, ks) : -1;
+    int label = ok ? segment_label(s, c, m, k, ks) : -1;
+    if (use_end && ok && c >= d && c < d + k) label = end.order[c - d];
     double col[MM];
     // rows d..d+k-1 and the squared sums below them are all the walk needs
     segment_qr<MM>(R0, stats->scale, m, label, c, col, piv_col[hw], min(m, d + k));
@@ -64,7 +71,7 @@ __global__ __launch_bounds__(256) void anchor_kernel(const double *__restrict__ 
         if (r >= 0 && r < k) an[r * 32 + l] = TO(col[i]);
         if (r >= k) t = fma(col[i], col[i], t);
     }
-    tail[seg * 32 + l] = TO(t);
+    if (tail) tail[seg * 32 + l] = TO(t);
 }
 
 // Anchors of many datasets in one launch: half-wave h of the launch takes the
@@ -129,15 +136,16 @@ hipError_t launch_anchors_batched_f32(const BatchItem *items, const int64_t *seg
 }
 
 template <typename TO>
-hipError_t launch_anchors(const double *R0, const ColStats *stats, int m, int k, int ks,
-                          int64_t nseg, TO *anchor, TO *tail, hipStream_t s) {
+static hipError_t launch_anchors_impl(const double *R0, const ColStats *stats, int m, int k,
+                                      int ks, int64_t nseg, TO *anchor, TO *tail,
+                                      const WalkEnd &end, int use_end, hipStream_t s) {
     const dim3 grid(unsigned((nseg + ANCHOR_HALVES - 1) / ANCHOR_HALVES)), block(256);
     const int mm = (m + 3) / 4 * 4;
     switch (mm) {
 #define GS_ANCHOR_CASE(MMV)                                                                   \
     case MMV:                                                                                 \
         hipLaunchKernelGGL((anchor_kernel<MMV, TO>), grid, block, 0, s, R0, stats, m, k, ks, \
-                           nseg, anchor, tail);                                               \
+                           nseg, anchor, tail, end, use_end);                                 \
         break;
         GS_ANCHOR_CASE(4)
         GS_ANCHOR_CASE(8)
@@ -153,9 +161,25 @@ hipError_t launch_anchors(const double *R0, const ColStats *stats, int m, int k,
     return hipGetLastError();
 }
 
+template <typename TO>
+hipError_t launch_anchors(const double *R0, const ColStats *stats, int m, int k, int ks,
+                          int64_t nseg, TO *anchor, TO *tail, hipStream_t s) {
+    return launch_anchors_impl<TO>(R0, stats, m, k, ks, nseg, anchor, tail, WalkEnd{}, 0, s);
+}
+
+template <typename TO>
+hipError_t launch_anchors_end(const double *R0, const ColStats *stats, int m, int k, int ks,
+                              int64_t nseg, const WalkEnd &end, TO *anchor, hipStream_t s) {
+    return launch_anchors_impl<TO>(R0, stats, m, k, ks, nseg, anchor, nullptr, end, 1, s);
+}
+
 template hipError_t launch_anchors<float>(const double *, const ColStats *, int, int, int, int64_t,
                                           float *, float *, hipStream_t);
 template hipError_t launch_anchors<double>(const double *, const ColStats *, int, int, int, int64_t,
                                            double *, double *, hipStream_t);
+template hipError_t launch_anchors_end<float>(const double *, const ColStats *, int, int, int,
+                                              int64_t, const WalkEnd &, float *, hipStream_t);
+template hipError_t launch_anchors_end<double>(const double *, const ColStats *, int, int, int,
+                                               int64_t, const WalkEnd &, double *, hipStream_t);
 
 }  // namespace gs

@@ -41,6 +41,8 @@ void free_device(gs_plan_s *p) {
     (void)hipFree(p->d_partial);
     (void)hipFree(p->d_B);
     (void)hipFree(p->d_K);
+    (void)hipFree(p->d_anchor_end);
+    p->d_anchor_end = nullptr;
     (void)hipFree(p->d_ups);
     p->d_ups = nullptr;
     p->beta_k = 0;
@@ -70,8 +72,8 @@ int64_t workspace_bytes(const gs_plan_s *p, int64_t n, bool backward) {
                 int64_t(sizeof(int)) * 4 + int64_t(sizeof(ColStats)) +
                 2 * qr_workspace_elems(n, p->m) * 8;
     if (backward)
-        b += p->nseg * p->k * 32 * 8 + p->nseg * 32 * 8 + p->nseg * m2 * 8 +
-             adjoint_partial_chunks(p->nseg) * m2 * 8 + 2 * m2 * 8;
+        b += p->nseg * p->k * 32 * 8 * (p->k >= ADJ_END_MIN_K ? 2 : 1) + p->nseg * 32 * 8 +
+             p->nseg * m2 * 8 + adjoint_partial_chunks(p->nseg) * m2 * 8 + 2 * m2 * 8;
     return b;
 }
 
@@ -229,12 +231,16 @@ int ensure_adjoint_workspace(gs_plan_s *p, int64_t n) {
         (e = hipMalloc(&p->d_vout, size_t(p->nseg) * m2 * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&p->d_partial, nch * m2 * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&p->d_B, m2 * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&p->d_K, m2 * sizeof(double))) != hipSuccess) {
+        (e = hipMalloc(&p->d_K, m2 * sizeof(double))) != hipSuccess ||
+        (p->k >= ADJ_END_MIN_K &&
+         (e = hipMalloc(&p->d_anchor_end, size_t(p->nseg) * p->k * 32 * sizeof(double))) !=
+             hipSuccess)) {
         (void)hipFree(p->d_anchorbar);
         (void)hipFree(p->d_tailbar);
         (void)hipFree(p->d_vout);
         (void)hipFree(p->d_partial);
         (void)hipFree(p->d_B);
+        (void)hipFree(p->d_K);
         p->d_anchorbar = p->d_tailbar = p->d_vout = p->d_partial = p->d_B = p->d_K = nullptr;
         return fail(GS_ENOMEM, std::string("adjoint workspace allocation failed: ") +
                                    hipGetErrorString(e));
@@ -262,8 +268,16 @@ int score_backward_impl(gs_plan_s *p, const double *X, int64_t n, int m, int64_t
     const bool reuse = p->reuse_front && p->front_x == X && p->front_n == n &&
                        p->front_ldx == ldx && p->front_elem == int(sizeof(T));
     if (!reuse && (st = front_half<T>(p, X, n, m, ldx, s, nullptr)) != GS_OK) return st;
-    hipError_t e = launch_walk_adjoint<T>(p, static_cast<const T *>(p->d_anchor),
-                                          static_cast<const T *>(p->d_tail), dscores,
+    hipError_t e = hipSuccess;
+    T *an_end = nullptr;  // long walks start the reverse walk from their end state
+    if (p->k >= ADJ_END_MIN_K) {
+        an_end = static_cast<T *>(p->d_anchor_end);
+        if ((e = launch_anchors_end<T>(p->d_r0, p->d_stats, p->m, p->k, p->ks, p->nseg, p->end,
+                                       an_end, s)) != hipSuccess)
+            return hip_fail(e, "end-state anchor launch");
+    }
+    e = launch_walk_adjoint<T>(p, static_cast<const T *>(p->d_anchor),
+                                          static_cast<const T *>(p->d_tail), an_end, dscores,
                                           p->d_anchorbar, p->d_tailbar, n, what == GS_OUT_BIC, s);
     if (e != hipSuccess) return hip_fail(e, "walk adjoint launch");
     if ((e = launch_qr_adjoint_chain(p, p->d_r0, p->d_stats, what == GS_OUT_BIC, p->d_anchorbar,

@@ -59,11 +59,24 @@ struct ReducePartials {
     ReduceStage *stage = nullptr;  // m x GS_REDUCE_SPLIT
 };
 
+// The walk's state after its last sub-walk, the same for every segment: position r of
+// the walked block holds variable order[r], and the inner block starts at middle row z.
+struct WalkEnd {
+    int8_t order[32];
+    int z;
+};
+
+// The adjoint starts the reverse walk from anchors formed in the final ordering (one QR
+// per segment) instead of replaying the walk, for segments of at least this many walked
+// variables (shorter walks replay faster than the extra QR launch).
+constexpr int ADJ_END_MIN_K = 10;
+
 struct gs_plan_s {
     uint64_t id = 0;  // unique per plan created in this process
     int m = 0, k = 0, ks = 0, q = 0;
     int64_t nseg = 0, nsub = 0;
     std::vector<uint32_t> prog;  // 2 words per sub-walk (layout in walk_program.hpp)
+    WalkEnd end{};               // the walk's state after the last sub-walk
     // segments packed into 64-lane waves: for wave w and lane x, lane_seg[64 w + x] is
     // the segment code (or -1) and lane_loc[64 w + x] the column slot inside it
     int64_t nwaves = 0;
@@ -83,7 +96,9 @@ struct gs_plan_s {
     void *d_anchor = nullptr;    // nseg x k x 32 (float or double)
     void *d_tail = nullptr;      // nseg x 32
     int *d_status = nullptr;
-    // adjoint workspace (allocated on the first backward call)
+    // adjoint workspace (allocated on the first backward call); d_anchor_end: anchors in
+    // the walk's final ordering (k >= ADJ_END_MIN_K only)
+    void *d_anchor_end = nullptr;
     double *d_anchorbar = nullptr;  // nseg x k x 32
     double *d_tailbar = nullptr;    // nseg x 32
     double *d_vout = nullptr;       // nseg x m x m
@@ -211,6 +226,11 @@ int pack_waves(gs_plan_s *p);
 template <typename T>
 hipError_t launch_anchors(const double *R0, const ColStats *stats, int m, int k, int ks,
                           int64_t nseg, T *anchor, T *tail, hipStream_t s);
+// The same rows of every segment with its walked block in the final ordering of the
+// walk (end), in the row layout of that state; the tails are those of the start.
+template <typename T>
+hipError_t launch_anchors_end(const double *R0, const ColStats *stats, int m, int k, int ks,
+                              int64_t nseg, const WalkEnd &end, T *anchor, hipStream_t s);
 
 // Device tables a walk launch reads besides its anchors: the plan's program and packed
 // lane tables, the dataset's status word and column statistics.
@@ -253,10 +273,12 @@ hipError_t launch_anchors_batched_f32(const BatchItem *items, const int64_t *seg
                                       int64_t total_segs, int mmax, hipStream_t s);
 
 // Adjoint (adjoint.hip)
+// anchor_end: anchors of the walk's final state (launch_anchors_end), from which the
+// reverse walk starts; nullptr: the walk is replayed from `anchor` first.
 template <typename T>
-hipError_t launch_walk_adjoint(const gs_plan_s *p, const T *anchor, const T *tail, const T *dscores,
-                               double *anchorbar, double *tailbar, int64_t n, bool bic,
-                               hipStream_t s);
+hipError_t launch_walk_adjoint(const gs_plan_s *p, const T *anchor, const T *tail,
+                               const T *anchor_end, const T *dscores, double *anchorbar,
+                               double *tailbar, int64_t n, bool bic, hipStream_t s);
 int64_t adjoint_partial_chunks(int64_t nseg);
 hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const ColStats *stats,
                                    bool bic, const double *anchorbar,

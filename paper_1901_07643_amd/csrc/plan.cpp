@@ -157,6 +157,60 @@ int pack_waves(gs_plan_s *p) {
     return GS_OK;
 }
 
+// The walked block's ordering and the inner block's position after the last sub-walk:
+// the state a replay of the whole walk ends in (the reverse walk of the adjoint starts
+// there).  The same for every segment.
+template <int KS>
+static void walk_end_state(gs_plan_s *p) {
+    constexpr auto &P = kInner<KS>;
+    constexpr int N = InnerProgram<KS>::N;
+    const int k = p->k, q = p->q;
+    std::vector<int> order(static_cast<size_t>(k));
+    for (int i = 0; i < q; ++i) order[size_t(i)] = KS + i;
+    for (int i = 0; i < KS; ++i) order[size_t(q + i)] = i;
+    int z = q;
+    for (int64_t t = 0; t < p->nsub; ++t) {
+        const uint32_t w1 = p->prog[size_t(2 * t + 1)];
+        const bool fwd = (t & 1) == 0;
+        if (w1 & SubWord::kHasTransition) {
+            if (w1 & SubWord::kHasMid) {
+                const int j = int((w1 >> 2) & 31);
+                const int pos = j < z ? j : j + KS;
+                std::swap(order[size_t(pos)], order[size_t(pos + 1)]);
+            }
+            if (w1 & SubWord::kCrossLeft) {  // the first middle variable behind moves in front
+                const int v = order[size_t(z + KS)];
+                for (int i = z + KS; i > z; --i) order[size_t(i)] = order[size_t(i - 1)];
+                order[size_t(z)] = v;
+                ++z;
+            } else {  // the last middle variable in front moves behind
+                const int v = order[size_t(z - 1)];
+                for (int i = z - 1; i < z - 1 + KS; ++i) order[size_t(i)] = order[size_t(i + 1)];
+                order[size_t(z - 1 + KS)] = v;
+                --z;
+            }
+        }
+        for (int st = 0; st < N; ++st) {
+            const int j = fwd ? P.j_f[st] : P.j_r[st];
+            std::swap(order[size_t(z + j)], order[size_t(z + j + 1)]);
+        }
+    }
+    for (int i = 0; i < 32; ++i) p->end.order[i] = int8_t(i < k ? order[size_t(i)] : -1);
+    p->end.z = z;
+}
+
+static void walk_end_state_ks(gs_plan_s *p) {
+    switch (p->ks) {
+        case 1: walk_end_state<1>(p); break;
+        case 2: walk_end_state<2>(p); break;
+        case 3: walk_end_state<3>(p); break;
+        case 4: walk_end_state<4>(p); break;
+        case 5: walk_end_state<5>(p); break;
+        case 6: walk_end_state<6>(p); break;
+        default: break;
+    }
+}
+
 // ---- host simulation of a plan (for gs_plan_count_emissions) -------------------
 
 template <int KS>
@@ -278,6 +332,10 @@ static int simulate(const gs_plan_s *p, int32_t *counts, int64_t len) {
                 if (emit_prefix(z + j + 1)) return fail(GS_EINVAL, "simulate: index range");
             }
         }
+        // the state the adjoint's end-state anchors are formed in
+        if (z != p->end.z) return fail(GS_EINVAL, "simulate: end position of the inner block");
+        for (int i = 0; i < k; ++i)
+            if (order[size_t(i)] != p->end.order[i]) return fail(GS_EINVAL, "simulate: end ordering");
     }
     return GS_OK;
 }
@@ -337,6 +395,7 @@ int gs_plan_tuned(int m, int k, int ks, gs_plan_t **out) {
     p->q = k - ks;
     p->nseg = int64_t(1) << (m - k);
     int st = build_program(p);
+    if (st == GS_OK) walk_end_state_ks(p);
     if (st == GS_OK) st = pack_waves(p);
     if (st != GS_OK) {
         delete p;
