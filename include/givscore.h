@@ -264,7 +264,7 @@ int gs_score_all_f64(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t
  * rules of the segment-anchor QRs and of R0 are applied in FP64; all sums run in a
  * fixed order, so the result is reproducible bit for bit.  Workspace: about
  * 2^(m-k) (k + m^2/32 + 1) x 256 bytes, plus 2^(m-k) k x 256 bytes for segments of
- * k >= 10 (whose reverse walk starts from anchors formed in the walk's final ordering
+ * k >= 9 (whose reverse walk starts from anchors formed in the walk's final ordering
  * instead of a replay), allocated on the first call. */
 int gs_score_backward(gs_plan_t *plan, const double *X, int64_t n, int m, int64_t ldx,
                       const float *dscores, int what, double *dX, int64_t lddx, void *stream);

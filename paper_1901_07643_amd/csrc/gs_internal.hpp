@@ -69,7 +69,7 @@ struct WalkEnd {
 // The adjoint starts the reverse walk from anchors formed in the final ordering (one QR
 // per segment) instead of replaying the walk, for segments of at least this many walked
 // variables (shorter walks replay faster than the extra QR launch).
-constexpr int ADJ_END_MIN_K = 10;
+constexpr int ADJ_END_MIN_K = 9;
 
 struct gs_plan_s {
     uint64_t id = 0;  // unique per plan created in this process
