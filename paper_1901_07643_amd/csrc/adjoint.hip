@@ -639,7 +639,10 @@ hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const C
                                    double *K, const double *X, int64_t n, int64_t ldx, double *dX,
                                    int64_t lddx, hipStream_t s) {
     const int m = p->m;
-    const int mm = (m + 3) / 4 * 4;
+    // columns padded to a multiple of 4; above 24 to 32: the instance for 28 columns
+    // exceeds the register file and spills to scratch, the one for 32 does not (the
+    // one for 24 spills less and is still faster than padding to 32)
+    const int mm = m > 24 ? 32 : (m + 3) / 4 * 4;
     const dim3 ag(unsigned((p->nseg + 1) / 2));
     switch (mm) {
 #define GS_AADJ_CASE(MMV)                                                                        \
@@ -653,7 +656,6 @@ hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const C
         GS_AADJ_CASE(16)
         GS_AADJ_CASE(20)
         GS_AADJ_CASE(24)
-        GS_AADJ_CASE(28)
         GS_AADJ_CASE(32)
 #undef GS_AADJ_CASE
         default: return hipErrorInvalidValue;
@@ -679,7 +681,6 @@ hipError_t launch_qr_adjoint_chain(const gs_plan_s *p, const double *R0, const C
         GS_FK_CASE(16)
         GS_FK_CASE(20)
         GS_FK_CASE(24)
-        GS_FK_CASE(28)
         GS_FK_CASE(32)
 #undef GS_FK_CASE
         default: return hipErrorInvalidValue;
