@@ -365,10 +365,12 @@ __device__ __forceinline__ void walk_body(const T *__restrict__ anchor, const T 
 
     // FP32, inner block 5, table written: the lines of a sub-walk wait in the LDS stage and
     // leave during the next sub-walk, one 16-byte store instruction (8 whole lines) every
-    // three inner steps, so that the waves' stores are spread over the walk instead of
-    // coming all at once at the end of each sub-walk
+    // three inner steps.  Each stage read completes behind the next step's broadcasts, and
+    // only one chunk is held in registers at a time (not all eight at the sub-walk's end).
     constexpr bool kStaged =
         std::is_same_v<T, float> && KS == 5 && (MODE == WALK_STORE || MODE == WALK_COUNT);
+    static_assert(!kStaged || InnerProgram<KS>::N >= 3 * STAGE_CHUNKS,
+                  "every chunk must leave within the next sub-walk's inner steps");
     const int ch = lane64 & 7;
     uint64_t pd = 0;
     float4 pv = make_float4(0.f, 0.f, 0.f, 0.f);
