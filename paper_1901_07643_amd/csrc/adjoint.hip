@@ -4,7 +4,8 @@
 // X -> R0 -> segment anchors -> walk -> RSS -> score backwards:
 //   1. walk_adjoint_kernel: per segment, the walk is replayed to its end (or, for long
 //      walks, its end state is formed directly as the R of the final ordering, one QR
-//      per segment like the anchors), then undone step by step.  Every Givens step is a reflector, its own inverse, and the
+//      per segment like the anchors), then undone step by step.  Every Givens step is a
+//      reflector, its own inverse, and the
 //      rotation of a step is recovered from the matrix after the step: the column that
 //      moved from position j to j+1 holds (c x, s x) there, x > 0 its old diagonal
 //      (anchors have a non-negative diagonal and every step keeps it so).  Nothing is
@@ -174,15 +175,14 @@ __device__ __forceinline__ void fwd_step(T &x, T &y, int paddr, bool is_piv) {
 }
 
 // Undo one forward step and carry its adjoint back.  On entry (x, y) are rows j, j+1
-// after the step and (xb, yb) their adjoints; paddr / is_piv name the pivot column,
-// maddr / is_mov the column that moved from j to j+1.  On return: rows and adjoints
-// before the step.
+// after the step and (xb, yb) their adjoints; is_piv marks the pivot column's lane (its
+// row-j entry after the step is rho), maddr / is_mov the column that moved from j to
+// j+1.  On return: rows and adjoints before the step.
 template <typename T>
-__device__ __forceinline__ void rev_step(T &x, T &y, T &xb, T &yb, int paddr, int maddr,
-                                         bool is_piv, bool is_mov) {
+__device__ __forceinline__ void rev_step(T &x, T &y, T &xb, T &yb, int maddr, bool is_piv,
+                                         bool is_mov) {
     T c, s;
     cs_from(bcast_r(x, maddr), bcast_r(y, maddr), c, s);
-    const T rho = bcast_r(x, paddr);
     const T xa = x, ya = y;
     const T xba = xb, yba = is_piv ? T(0) : yb;  // the pivot's new row-(j+1) entry is a constant
     const T x0 = c * xa + s * ya;
@@ -191,8 +191,9 @@ __device__ __forceinline__ void rev_step(T &x, T &y, T &xb, T &yb, int paddr, in
     T yb0 = s * xba - c * yba;
     const T cb = half_sum(xba * x0 - yba * y0);
     const T sb = half_sum(xba * y0 + yba * x0);
-    // the pivot lane carries the adjoints of c and s (through rho) back to its rows
-    const T rinv = (is_piv && rho != T(0)) ? recip_r(rho) : T(0);
+    // the pivot lane carries the adjoints of c and s (through rho) back to its rows; its
+    // own row-j entry after the step is rho
+    const T rinv = (is_piv && xa != T(0)) ? recip_r(xa) : T(0);
     const T t = (cb * s - sb * c) * rinv;
     xb0 += s * t;
     yb0 -= c * t;
@@ -384,7 +385,7 @@ __attribute__((amdgpu_waves_per_eu(kAdjMinWaves<T, KS>, 8))) void walk_adjoint_k
             Ib[J + 1] += T(2) * I[J + 1] * Sb[J + 1];
             Sb[J + 2] += Sb[J + 1];
             Sb[J + 1] = T(0);
-            rev_step(I[J], I[J + 1], Ib[J], Ib[J + 1], base + PV * 4, base + MV * 4, lane == PV,
+            rev_step(I[J], I[J + 1], Ib[J], Ib[J + 1], base + MV * 4, lane == PV,
                      lane == MV);
             sfx[J + 1] = I[J + 1] * I[J + 1] + sfx[J + 2];
         });
@@ -411,7 +412,7 @@ __attribute__((amdgpu_waves_per_eu(kAdjMinWaves<T, KS>, 8))) void walk_adjoint_k
                 static_for_r<0, KS>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
                     T x = carry, y = I[i], xb = carryb, yb = Ib[i];
-                    rev_step(x, y, xb, yb, base + v * 4, base + ord[i] * 4, lane == v,
+                    rev_step(x, y, xb, yb, base + ord[i] * 4, lane == v,
                              lane == ord[i]);
                     I[i] = x;
                     Ib[i] = xb;
@@ -425,7 +426,7 @@ __attribute__((amdgpu_waves_per_eu(kAdjMinWaves<T, KS>, 8))) void walk_adjoint_k
                 static_for_r<0, KS>([&](auto ic) {
                     constexpr int i = KS - 1 - decltype(ic)::value;
                     T x = I[i], y = carry, xb = Ib[i], yb = carryb;
-                    rev_step(x, y, xb, yb, base + ord[i] * 4, base + v * 4, lane == ord[i],
+                    rev_step(x, y, xb, yb, base + v * 4, lane == ord[i],
                              lane == v);
                     carry = x;
                     carryb = xb;
@@ -440,7 +441,7 @@ __attribute__((amdgpu_waves_per_eu(kAdjMinWaves<T, KS>, 8))) void walk_adjoint_k
                 const int j = int((w1 >> 2) & 31), piv = int((w1 >> 8) & 31);
                 const int mv = int((w0 >> 21) & 31);
                 T x = L[j][lane], y = L[j + 1][lane], xb = Lb[j][lane], yb = Lb[j + 1][lane];
-                rev_step(x, y, xb, yb, base + piv * 4, base + mv * 4, lane == piv, lane == mv);
+                rev_step(x, y, xb, yb, base + mv * 4, lane == piv, lane == mv);
                 L[j][lane] = x;
                 L[j + 1][lane] = y;
                 Lb[j][lane] = xb;
