@@ -83,16 +83,23 @@ __device__ __forceinline__ double xor16_r(double v) {
                                             (unsigned long long)(unsigned)lo));
 }
 
-// sum over the 32 lanes of this half-wave (one segment), in every lane: pairs (lane ^ 1),
-// quads (lane ^ 2), the two quads of each 8 (mirror inside 8), the two 8s of each row
-// (mirror inside 16), then the two rows (lane ^ 16)
+// Sums of a and of b over the 32 lanes of this half-wave (one segment), in every lane:
+// pairs (lane ^ 1), quads (lane ^ 2), the two quads of each 8 (mirror inside 8), the two
+// 8s of each row (mirror inside 16), then the two rows (lane ^ 16).  The two chains
+// alternate, so each DPP add reads a value written two instructions earlier: a single
+// chain needs wait states between a VALU write and a DPP read of it.
 template <typename T>
-__device__ __forceinline__ T half_sum(T v) {
-    v += dpp_r<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-    v += dpp_r<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-    v += dpp_r<0x141>(v);  // row_half_mirror
-    v += dpp_r<0x140>(v);  // row_mirror
-    return v + xor16_r(v);
+__device__ __forceinline__ void half_sum2(T &a, T &b) {
+    a += dpp_r<0xB1>(a);  // quad_perm [1, 0, 3, 2]
+    b += dpp_r<0xB1>(b);
+    a += dpp_r<0x4E>(a);  // quad_perm [2, 3, 0, 1]
+    b += dpp_r<0x4E>(b);
+    a += dpp_r<0x141>(a);  // row_half_mirror
+    b += dpp_r<0x141>(b);
+    a += dpp_r<0x140>(a);  // row_mirror
+    b += dpp_r<0x140>(b);
+    a += xor16_r(a);
+    b += xor16_r(b);
 }
 
 // 1 / x: the hardware reciprocal in FP32 (within 1 ulp), a division in FP64
@@ -189,8 +196,9 @@ __device__ __forceinline__ void rev_step(T &x, T &y, T &xb, T &yb, int maddr, bo
     const T y0 = is_mov ? T(0) : s * xa - c * ya;
     T xb0 = c * xba + s * yba;
     T yb0 = s * xba - c * yba;
-    const T cb = half_sum(xba * x0 - yba * y0);
-    const T sb = half_sum(xba * y0 + yba * x0);
+    T cb = xba * x0 - yba * y0;
+    T sb = xba * y0 + yba * x0;
+    half_sum2(cb, sb);
     // the pivot lane carries the adjoints of c and s (through rho) back to its rows; its
     // own row-j entry after the step is rho
     const T rinv = (is_piv && xa != T(0)) ? recip_r(xa) : T(0);
